@@ -1,0 +1,221 @@
+/*
+ * spmv.h - C ABI of the MI355X (gfx950) sparse matrix-vector library.
+ *
+ * The library computes y = alpha * A * x + beta * y (the SpMV product Y = A X
+ * of the paper's background section on SpMV processing, with BLAS scaling)
+ * for a sparse A held in one of the formats the run-time mode chooses
+ * between, and picks the fastest format for a given matrix from its sparsity
+ * features (paper, Method: run-time optimisation mode; sparsity features
+ * table).
+ *
+ * Conventions for every function:
+ *   - Indices are 0-based int32. Values are FP32 or FP64 (spmv_dtype).
+ *   - A "device pointer" is memory allocated on the current HIP device
+ *     (hipMalloc or torch). A "host pointer" is ordinary CPU memory.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *     All device work is enqueued on it.
+ *   - Every function returns a status and never throws or aborts across the
+ *     ABI. spmv_last_error() gives a message for the calling thread.
+ *   - Handles are owned by the library; spmv_create copies its inputs. A
+ *     handle is not thread-safe: calls on one handle must not overlap.
+ *   - The current device at spmv_create is the handle's device; later calls
+ *     on the handle must run with that device current.
+ */
+#ifndef SPMV_H
+#define SPMV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum spmv_status {
+    SPMV_OK = 0,
+    SPMV_ERR_INVALID_ARG = 1,   /* bad pointer, size, enum, x == y, ...          */
+    SPMV_ERR_OUT_OF_BOUNDS = 2, /* a COO row/col index outside the matrix         */
+    SPMV_ERR_DUPLICATE = 3,     /* two COO entries with the same (row, col)       */
+    SPMV_ERR_NOT_CONVERTED = 4, /* format not built yet on this handle            */
+    SPMV_ERR_NOT_APPLICABLE = 5,/* ELL padded size would exceed 8 * nnz           */
+    SPMV_ERR_OOM = 6,           /* device allocation failed                       */
+    SPMV_ERR_HIP = 7,           /* a HIP runtime call failed                      */
+    SPMV_ERR_NO_MODEL = 8       /* selector weights not loaded                    */
+} spmv_status;
+
+/* Storage formats. The numbering is also the selector's class order. */
+typedef enum spmv_format {
+    SPMV_FMT_CSR = 0, /* row_ptr[n_rows+1], col[nnz], val[nnz], rows in order    */
+    SPMV_FMT_COO = 1, /* row[nnz], col[nnz], val[nnz], sorted by (row, col)       */
+    SPMV_FMT_ELL = 2, /* col/val [K][pitch], column-major, pitch = roundup(n,64)  */
+    SPMV_FMT_HYB = 3  /* ELL part of width K_h + COO tail of the other entries    */
+} spmv_format;
+#define SPMV_NUM_FORMATS 4
+
+typedef enum spmv_dtype { SPMV_F32 = 0, SPMV_F64 = 1 } spmv_dtype;
+
+/* Kernel families behind the formats (a variant is one compiled instance). */
+typedef enum spmv_kernel {
+    SPMV_KERNEL_CSR_SCALAR = 0, /* one thread per row                             */
+    SPMV_KERNEL_CSR_VECTOR = 1, /* `lanes` lanes of a wavefront per row           */
+    SPMV_KERNEL_COO = 2,        /* nnz tiles, segmented reduction by row          */
+    SPMV_KERNEL_ELL = 3,        /* `lanes` consecutive rows per thread            */
+    SPMV_KERNEL_HYB = 4         /* ELL part (`lanes` rows/thread) + COO tail      */
+} spmv_kernel;
+
+typedef enum spmv_select_mode {
+    SPMV_SELECT_MODEL = 0,      /* features -> selector network -> argmax         */
+    SPMV_SELECT_EXHAUSTIVE = 1, /* convert all, tune and time all, take the best  */
+    SPMV_SELECT_RULE = 2        /* fixed thresholds on the features               */
+} spmv_select_mode;
+
+typedef struct spmv_matrix_s *spmv_handle;
+typedef struct spmv_batch_s *spmv_batch;
+
+/* Description of one compiled kernel instance. */
+typedef struct spmv_variant_info {
+    int32_t kernel; /* spmv_kernel                                                */
+    int32_t block;  /* workgroup size (threads)                                    */
+    int32_t lanes;  /* CSR vector: lanes per row; ELL/HYB: rows per thread;
+                       COO: entries per thread; CSR scalar: 1                      */
+    int32_t unroll; /* independent loads in flight per lane                        */
+} spmv_variant_info;
+
+/* Borrowed view of a format's device arrays; valid until spmv_destroy or a
+ * re-conversion of that format. Fields a format does not use are 0 / NULL. */
+typedef struct spmv_arrays {
+    int32_t format, dtype, n_rows, n_cols;
+    int64_t nnz;      /* stored entries of the matrix                           */
+    int32_t K, pitch; /* ELL / HYB-ELL width and row pitch                       */
+    int64_t nnz_tail; /* HYB: entries in the COO tail                            */
+    const int32_t *row_ptr, *row, *col;
+    const void *val;
+    const int32_t *ell_col;
+    const void *ell_val;
+    const int32_t *tail_row, *tail_col;
+    const void *tail_val;
+} spmv_arrays;
+
+/* ---- matrix lifetime ----------------------------------------------------- */
+
+/* Ingest a COO matrix (the input format of the paper's run-time mode, Results:
+ * run-time prediction overhead) and build its canonical COO and CSR forms on
+ * the device (CSR: paper, Background, popular SpMV formats).
+ *   row, col: int32[nnz], val: float[nnz] or double[nnz] per `dt`; host
+ *   pointers if on_device == 0, device pointers otherwise; any order. The
+ *   caller keeps ownership; the library copies them.
+ *   n_rows, n_cols >= 0; 0 <= nnz <= INT32_MAX. nnz == 0 is legal.
+ * Entries are sorted by (row, col). Explicit zeros are kept as entries.
+ * Errors: INVALID_ARG (sizes, NULL pointers with nnz > 0, dtype),
+ *         OUT_OF_BOUNDS (an index outside [0,n_rows) x [0,n_cols)),
+ *         DUPLICATE (a repeated (row, col)), OOM, HIP.
+ * Synchronises `stream`. On error *out is set to NULL. */
+spmv_status spmv_create(spmv_handle *out, int32_t n_rows, int32_t n_cols, int64_t nnz,
+                        const int32_t *row, const int32_t *col, const void *val, spmv_dtype dt,
+                        int on_device, void *stream);
+
+/* Free a handle and all its device arrays. NULL is ignored. Synchronises the
+ * device. */
+void spmv_destroy(spmv_handle h);
+
+/* Build format `f` from the canonical CSR (paper, Background: ELL, and the
+ * run-time mode's conversion step). CSR and COO exist after spmv_create and
+ * return OK at once.
+ *   ELL: width K = longest row, pitch = roundup(n_rows, 64), slot (i, k) at
+ *        k * pitch + i, padding slots hold col -1 and val +0.0. Returns
+ *        NOT_APPLICABLE (and builds nothing) when pitch * K > 8 * nnz.
+ *   HYB: ELL part of width K_h plus the remaining entries as a COO tail in
+ *        (row, col) order. hyb_k < 0 chooses K_h by the Bell-Garland rule:
+ *        the largest k such that at least T = min(n_rows, max(4096,
+ *        ceil(n_rows/3))) rows hold k or more entries; hyb_k >= 0 forces it.
+ * A failed conversion leaves the handle's other formats intact.
+ * Errors: INVALID_ARG, NOT_APPLICABLE, OOM, HIP. Synchronises `stream`. */
+spmv_status spmv_convert(spmv_handle h, spmv_format f, int32_t hyb_k, void *stream);
+
+/* y = alpha * A * x + beta * y with the handle's current variant for `f`
+ * (paper, Background: SpMV processing on GPU). Asynchronous on `stream`.
+ *   x: device pointer, n_cols values of the handle's dtype.
+ *   y: device pointer, n_rows values; read only when beta != 0, so beta == 0
+ *      ignores NaN or garbage in y. x and y must not overlap.
+ *   alpha, beta: rounded to the handle's dtype.
+ * Rows with no entries get y = beta * y (or 0 when beta == 0).
+ * Errors: INVALID_ARG (NULL x/y with a nonzero dimension, x == y),
+ *         NOT_CONVERTED, HIP (launch failure). */
+spmv_status spmv_run(spmv_handle h, spmv_format f, double alpha, const void *x, double beta,
+                     void *y, void *stream);
+
+/* Borrowed device arrays of format `f` (see spmv_arrays). Errors:
+ * INVALID_ARG, NOT_CONVERTED. */
+spmv_status spmv_get_arrays(spmv_handle h, spmv_format f, spmv_arrays *view);
+
+/* ---- kernel variants and timing (the paper's compile-time mode picks thread
+ * block size and register/cache settings per matrix, Method: compile-time
+ * optimisation mode; here each format has a set of compiled instances and the
+ * fastest is chosen by timing) ---------------------------------------------- */
+
+/* Number of compiled variants of format f for dtype dt (0 for a bad enum). */
+int32_t spmv_variant_count(spmv_format f, spmv_dtype dt);
+
+/* Describe variant `idx` of (f, dt). Errors: INVALID_ARG. */
+spmv_status spmv_variant_describe(spmv_format f, spmv_dtype dt, int32_t idx,
+                                  spmv_variant_info *out);
+
+/* Select / query the variant spmv_run uses for format f on this handle.
+ * A new handle starts with a default chosen from its row-length statistics.
+ * Errors: INVALID_ARG. */
+spmv_status spmv_set_variant(spmv_handle h, spmv_format f, int32_t idx);
+spmv_status spmv_get_variant(spmv_handle h, spmv_format f, int32_t *idx);
+
+/* Time `reps` runs of format f with variant `variant` (-1 = current) after
+ * `warmup` untimed runs, y = 1 * A * x + 0 * y. If flush != 0 every timed run
+ * is preceded by a 1 GiB read sweep that evicts L2 and the Infinity Cache.
+ * Each run is bracketed by a pair of HIP events on `stream`.
+ *   out_ms: host pointer, float[reps], milliseconds per run.
+ * Errors: INVALID_ARG, NOT_CONVERTED, OOM (flush buffer), HIP.
+ * Synchronises `stream`. */
+spmv_status spmv_time(spmv_handle h, spmv_format f, int32_t variant, const void *x, void *y,
+                      int32_t warmup, int32_t reps, int flush, float *out_ms, void *stream);
+
+/* Autotune format f: time every variant (median of `reps` runs, flushed if
+ * flush != 0), make the fastest the handle's current variant, and return it.
+ *   best_idx, best_ms: host pointers (may be NULL).
+ * Errors: as spmv_time. Synchronises `stream`. */
+spmv_status spmv_tune(spmv_handle h, spmv_format f, const void *x, void *y, int32_t reps,
+                      int flush, int32_t *best_idx, float *best_ms, void *stream);
+
+/* ---- features and selection ---------------------------------------------- */
+
+/* The 12 sparsity features of the matrix, computed on the device (paper,
+ * Method: sparsity features table, extended), in this order:
+ *   0 n_rows, 1 nnz, 2 mean row length, 3 population variance of row
+ *   lengths, 4 standard deviation, 5 median row length (mean of the middle
+ *   two when n is even), 6 mode (most frequent length, smallest on ties),
+ *   7 ELL ratio nnz / (n * max), 8 max row length, 9 bandwidth max |i - j|,
+ *   10 fill nnz / (n_rows * n_cols), 11 HYB tail fraction at the rule's K_h.
+ * Quantities with an empty denominator are 0.
+ *   out12: host pointer, float[12]. Synchronises `stream`. */
+spmv_status spmv_features(spmv_handle h, float *out12, void *stream);
+
+/* Choose the format for this matrix (paper, Method: run-time optimisation
+ * mode, steps 1-2; Predicting optimal configuration parameters).
+ *   MODEL: features -> selector network -> argmax over applicable formats
+ *          (requires spmv_selector_set_weights; else NO_MODEL).
+ *   EXHAUSTIVE: convert every format, tune each, take the fastest median.
+ *   RULE: fixed thresholds on the features.
+ *   out: host pointer. out_scores: host float[4] or NULL: logits (MODEL),
+ *   best median ms per format, +inf if not applicable (EXHAUSTIVE), or 0/1
+ *   votes (RULE). The chosen format is converted before return.
+ * Errors: INVALID_ARG, NO_MODEL, OOM, HIP. Synchronises `stream`. */
+spmv_status spmv_select_format(spmv_handle h, spmv_select_mode m, spmv_format *out,
+                               float *out_scores, void *stream);
+
+/* ---- diagnostics ------------------------------------------------------------ */
+
+const char *spmv_status_string(spmv_status s);
+/* Message of the calling thread's last failing call ("" if none). */
+const char *spmv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPMV_H */

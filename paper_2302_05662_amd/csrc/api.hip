@@ -1,0 +1,286 @@
+// C ABI entry points of the library (declared in include/spmv.h).
+#include <cmath>
+#include <cstdarg>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace spmv {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+void fail(spmv_status s, const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    throw Error{s};
+}
+
+bool valid_format(spmv_format f) { return f >= SPMV_FMT_CSR && f <= SPMV_FMT_HYB; }
+
+bool format_built(const spmv_matrix_s *h, spmv_format f) {
+    switch (f) {
+        case SPMV_FMT_CSR:
+        case SPMV_FMT_COO: return true;
+        case SPMV_FMT_ELL: return h->ell.built;
+        case SPMV_FMT_HYB: return h->hyb.built;
+    }
+    return false;
+}
+
+void check_runnable(const spmv_matrix_s *h, spmv_format f) {
+    if (!h) fail(SPMV_ERR_INVALID_ARG, "NULL handle");
+    if (!valid_format(f)) fail(SPMV_ERR_INVALID_ARG, "bad format %d", (int)f);
+    if (!format_built(h, f)) fail(SPMV_ERR_NOT_CONVERTED, "format %d not converted", (int)f);
+}
+
+void convert(spmv_matrix_s *h, spmv_format f, int32_t hyb_k, hipStream_t s) {
+    switch (f) {
+        case SPMV_FMT_CSR:
+        case SPMV_FMT_COO: return;
+        case SPMV_FMT_ELL: build_ell(h, s); return;
+        case SPMV_FMT_HYB: build_hyb(h, hyb_k, s); return;
+    }
+}
+
+double tune_format(spmv_matrix_s *h, spmv_format f, const void *x, void *y, int32_t reps, int flush,
+                   int32_t *best_idx, hipStream_t s);  // timing.hip
+
+namespace {
+
+template <class V>
+__global__ void fill_kernel(V *p, int64_t n, V v) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        p[i] = v;
+}
+
+int env_int(const char *name, int dflt) {
+    const char *v = getenv(name);
+    return v && *v ? atoi(v) : dflt;
+}
+
+// Timing-based choice: every applicable format converted, tuned and timed.
+spmv_format select_exhaustive(spmv_matrix_s *h, float scores[4], hipStream_t s) {
+    const size_t vs = dtype_size(h->dt);
+    DevBuf x, y;
+    x.alloc(std::max<int64_t>(h->n_cols, 1) * vs);
+    y.alloc(std::max<int64_t>(h->n_rows, 1) * vs);
+    const int64_t nx = std::max<int32_t>(h->n_cols, 1);
+    if (h->dt == SPMV_F64) fill_kernel<double><<<256, 256, 0, s>>>(x.as<double>(), nx, 1.0);
+    else fill_kernel<float><<<256, 256, 0, s>>>(x.as<float>(), nx, 1.0f);
+    SPMV_CHECK_LAUNCH();
+    const int reps = std::max(1, env_int("SPMV_TUNE_REPS", 10));
+    const int flush = env_int("SPMV_TUNE_FLUSH", 1);
+    double best = INFINITY;
+    spmv_format bf = SPMV_FMT_CSR;
+    for (int fi = 0; fi < SPMV_NUM_FORMATS; ++fi) {
+        const spmv_format f = (spmv_format)fi;
+        double t = INFINITY;
+        bool ok = true;
+        if (!format_built(h, f)) {
+            try {
+                convert(h, f, -1, s);
+            } catch (const Error &e) {
+                if (e.status != SPMV_ERR_NOT_APPLICABLE) throw;
+                ok = false;
+                clear_error();
+            }
+        }
+        if (ok) t = tune_format(h, f, x.p, y.p, reps, flush, nullptr, s);
+        scores[fi] = (float)t;
+        if (t < best) { best = t; bf = f; }
+    }
+    return bf;
+}
+
+// Fixed thresholds on the features (a baseline for the learned selector).
+spmv_format select_rule(const float f[12], float votes[4]) {
+    const double mean = f[2], sd = f[4], ell_ratio = f[7], mx = f[8], tail = f[11];
+    spmv_format r = SPMV_FMT_CSR;
+    if (mean > 0 && sd / mean < 0.1 && ell_ratio >= 0.8) r = SPMV_FMT_ELL;
+    else if (mean > 0 && mx > 16 * mean && tail < 0.5) r = SPMV_FMT_HYB;
+    else if (mean < 4) r = SPMV_FMT_COO;
+    for (int i = 0; i < 4; ++i) votes[i] = (i == (int)r) ? 1.f : 0.f;
+    return r;
+}
+
+}  // namespace
+
+spmv_status select_model(spmv_matrix_s *h, const float feats[12], spmv_format *out, float scores[4],
+                         hipStream_t s);  // mlp.hip
+
+}  // namespace spmv
+
+using namespace spmv;
+
+extern "C" void spmv_destroy(spmv_handle h) {
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    delete h;
+}
+
+extern "C" spmv_status spmv_convert(spmv_handle h, spmv_format f, int32_t hyb_k, void *stream) {
+    return guard([&] {
+        if (!h) fail(SPMV_ERR_INVALID_ARG, "NULL handle");
+        if (!valid_format(f)) fail(SPMV_ERR_INVALID_ARG, "bad format %d", (int)f);
+        convert(h, f, hyb_k, (hipStream_t)stream);
+    });
+}
+
+extern "C" spmv_status spmv_run(spmv_handle h, spmv_format f, double alpha, const void *x,
+                                double beta, void *y, void *stream) {
+    return guard([&] {
+        check_runnable(h, f);
+        const size_t vs = dtype_size(h->dt);
+        if (h->n_cols > 0 && !x) fail(SPMV_ERR_INVALID_ARG, "x is NULL");
+        if (h->n_rows > 0 && !y) fail(SPMV_ERR_INVALID_ARG, "y is NULL");
+        if (x && y && h->n_rows > 0 && h->n_cols > 0) {
+            const char *xb = (const char *)x, *xe = xb + (size_t)h->n_cols * vs;
+            const char *yb = (const char *)y, *ye = yb + (size_t)h->n_rows * vs;
+            if (xb < ye && yb < xe) fail(SPMV_ERR_INVALID_ARG, "x and y overlap");
+        }
+        launch_spmv(h, f, h->variant[f], alpha, x, beta, y, (hipStream_t)stream);
+    });
+}
+
+extern "C" spmv_status spmv_get_arrays(spmv_handle h, spmv_format f, spmv_arrays *v) {
+    return guard([&] {
+        check_runnable(h, f);
+        if (!v) fail(SPMV_ERR_INVALID_ARG, "NULL view");
+        memset(v, 0, sizeof(*v));
+        v->format = f;
+        v->dtype = h->dt;
+        v->n_rows = h->n_rows;
+        v->n_cols = h->n_cols;
+        v->nnz = h->nnz;
+        switch (f) {
+            case SPMV_FMT_CSR:
+                v->row_ptr = h->row_ptr.as<int32_t>();
+                v->col = h->col.as<int32_t>();
+                v->val = h->val.p;
+                break;
+            case SPMV_FMT_COO:
+                v->row = h->row.as<int32_t>();
+                v->col = h->col.as<int32_t>();
+                v->val = h->val.p;
+                break;
+            case SPMV_FMT_ELL:
+                v->K = h->ell.K;
+                v->pitch = h->ell.pitch;
+                v->ell_col = h->ell.col.as<int32_t>();
+                v->ell_val = h->ell.val.p;
+                break;
+            case SPMV_FMT_HYB:
+                v->K = h->hyb.K;
+                v->pitch = h->hyb.pitch;
+                v->nnz_tail = h->hyb.nnz_tail;
+                v->ell_col = h->hyb.ell_col.as<int32_t>();
+                v->ell_val = h->hyb.ell_val.p;
+                v->tail_row = h->hyb.tail_row.as<int32_t>();
+                v->tail_col = h->hyb.tail_col.as<int32_t>();
+                v->tail_val = h->hyb.tail_val.p;
+                break;
+        }
+    });
+}
+
+extern "C" int32_t spmv_variant_count(spmv_format f, spmv_dtype dt) {
+    if (!valid_format(f)) return 0;
+    return variant_count(f, dt);
+}
+
+extern "C" spmv_status spmv_variant_describe(spmv_format f, spmv_dtype dt, int32_t idx,
+                                             spmv_variant_info *out) {
+    return guard([&] {
+        if (!valid_format(f) || !out || !variant_describe(f, dt, idx, out))
+            fail(SPMV_ERR_INVALID_ARG, "bad format/dtype/index");
+    });
+}
+
+extern "C" spmv_status spmv_set_variant(spmv_handle h, spmv_format f, int32_t idx) {
+    return guard([&] {
+        if (!h || !valid_format(f)) fail(SPMV_ERR_INVALID_ARG, "bad handle or format");
+        if (idx < 0 || idx >= variant_count(f, h->dt)) fail(SPMV_ERR_INVALID_ARG, "bad variant %d", idx);
+        h->variant[f] = idx;
+    });
+}
+
+extern "C" spmv_status spmv_get_variant(spmv_handle h, spmv_format f, int32_t *idx) {
+    return guard([&] {
+        if (!h || !valid_format(f) || !idx) fail(SPMV_ERR_INVALID_ARG, "bad argument");
+        *idx = h->variant[f];
+    });
+}
+
+extern "C" spmv_status spmv_features(spmv_handle h, float *out12, void *stream) {
+    return guard([&] {
+        if (!h || !out12) fail(SPMV_ERR_INVALID_ARG, "NULL argument");
+        compute_features(h, out12, nullptr, (hipStream_t)stream);
+    });
+}
+
+extern "C" spmv_status spmv_select_format(spmv_handle h, spmv_select_mode m, spmv_format *out,
+                                          float *out_scores, void *stream) {
+    return guard([&] {
+        if (!h || !out) fail(SPMV_ERR_INVALID_ARG, "NULL argument");
+        hipStream_t s = (hipStream_t)stream;
+        float scores[4] = {0, 0, 0, 0};
+        spmv_format f = SPMV_FMT_CSR;
+        if (m == SPMV_SELECT_EXHAUSTIVE) {
+            f = select_exhaustive(h, scores, s);
+        } else if (m == SPMV_SELECT_RULE || m == SPMV_SELECT_MODEL) {
+            float feats[12];
+            compute_features(h, feats, nullptr, s);
+            if (m == SPMV_SELECT_RULE) {
+                f = select_rule(feats, scores);
+                if (f == SPMV_FMT_ELL && h->nnz > 0 &&
+                    (int64_t)((h->n_rows + 63) / 64 * 64) * h->stats.max_len > 8 * h->nnz)
+                    f = SPMV_FMT_CSR;
+            } else {
+                spmv_status st = select_model(h, feats, &f, scores, s);
+                if (st != SPMV_OK) throw Error{st};
+            }
+            if (!format_built(h, f)) convert(h, f, -1, s);
+        } else {
+            fail(SPMV_ERR_INVALID_ARG, "bad select mode %d", (int)m);
+        }
+        *out = f;
+        if (out_scores) memcpy(out_scores, scores, sizeof(scores));
+    });
+}
+
+extern "C" const char *spmv_status_string(spmv_status s) {
+    switch (s) {
+        case SPMV_OK: return "ok";
+        case SPMV_ERR_INVALID_ARG: return "invalid argument";
+        case SPMV_ERR_OUT_OF_BOUNDS: return "index out of bounds";
+        case SPMV_ERR_DUPLICATE: return "duplicate entry";
+        case SPMV_ERR_NOT_CONVERTED: return "format not converted";
+        case SPMV_ERR_NOT_APPLICABLE: return "format not applicable";
+        case SPMV_ERR_OOM: return "out of device memory";
+        case SPMV_ERR_HIP: return "HIP runtime error";
+        case SPMV_ERR_NO_MODEL: return "no selector model loaded";
+    }
+    return "unknown status";
+}
+
+extern "C" const char *spmv_last_error(void) { return g_last_error.c_str(); }

@@ -1,0 +1,174 @@
+// Internal runtime of the SpMV library: handle layout, error plumbing and
+// small device helpers shared by the translation units. Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "spmv.h"
+
+namespace spmv {
+
+// ---- errors -------------------------------------------------------------------
+
+void set_error(const char *fmt, ...);
+void clear_error();
+
+struct Error {
+    spmv_status status;
+};
+
+[[noreturn]] void fail(spmv_status s, const char *fmt, ...);
+
+#define SPMV_HIP(call)                                                                     \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            ::spmv::fail(e_ == hipErrorOutOfMemory ? SPMV_ERR_OOM : SPMV_ERR_HIP,          \
+                         "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__,  \
+                         __LINE__);                                                        \
+    } while (0)
+
+#define SPMV_CHECK_LAUNCH() SPMV_HIP(hipGetLastError())
+
+// Run `body` and turn thrown spmv::Error into a status.
+template <class F>
+spmv_status guard(F &&body) {
+    try {
+        clear_error();
+        body();
+        return SPMV_OK;
+    } catch (const Error &e) {
+        return e.status;
+    } catch (...) {
+        set_error("unexpected C++ exception");
+        return SPMV_ERR_HIP;
+    }
+}
+
+// ---- device memory ------------------------------------------------------------
+
+// Owning device buffer (hipMalloc / hipFree).
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void alloc(size_t n) {
+        release();
+        if (n == 0) return;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            fail(SPMV_ERR_OOM, "hipMalloc(%zu bytes) failed: %s", n, hipGetErrorString(e));
+        }
+        bytes = n;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+inline size_t dtype_size(spmv_dtype dt) { return dt == SPMV_F64 ? 8 : 4; }
+
+// ---- the matrix handle ----------------------------------------------------------
+
+struct EllPart {
+    bool built = false;
+    int32_t K = 0, pitch = 0;
+    DevBuf col, val;
+};
+
+struct HybPart {
+    bool built = false;
+    int32_t K = 0, pitch = 0;
+    int64_t nnz_tail = 0;
+    DevBuf ell_col, ell_val, tail_row, tail_col, tail_val, partials;
+};
+
+// Row-length statistics kept from ingest (used by defaults and features).
+struct RowStats {
+    int32_t max_len = 0;
+};
+
+}  // namespace spmv
+
+struct spmv_matrix_s {
+    int device = 0;
+    int32_t n_rows = 0, n_cols = 0;
+    int64_t nnz = 0;
+    spmv_dtype dt = SPMV_F32;
+    // canonical COO / CSR: row[nnz], col[nnz], val[nnz] sorted by (row, col);
+    // row_ptr[n_rows + 1].
+    spmv::DevBuf row, col, val, row_ptr;
+    spmv::DevBuf coo_partials;  // per-tile carries of the COO kernel
+    spmv::EllPart ell;
+    spmv::HybPart hyb;
+    spmv::RowStats stats;
+    int32_t variant[SPMV_NUM_FORMATS] = {0, 0, 0, 0};
+};
+
+namespace spmv {
+
+// ---- shared host-side helpers implemented in the .hip files ---------------------
+
+// ingest.hip
+void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s);
+int32_t device_max_row_len(const int32_t *row_ptr, int32_t n_rows, hipStream_t s);
+
+// convert.hip
+void build_ell(spmv_matrix_s *h, hipStream_t s);
+void build_hyb(spmv_matrix_s *h, int32_t hyb_k, hipStream_t s);
+int32_t hyb_rule_width(spmv_matrix_s *h, hipStream_t s);
+
+// kernels.hip
+int32_t variant_count(spmv_format f, spmv_dtype dt);
+bool variant_describe(spmv_format f, spmv_dtype dt, int32_t idx, spmv_variant_info *out);
+int32_t default_variant(const spmv_matrix_s *h, spmv_format f);
+void launch_spmv(const spmv_matrix_s *h, spmv_format f, int32_t variant, double alpha,
+                 const void *x, double beta, void *y, hipStream_t s);
+int64_t coo_partials_bytes(int64_t nnz, spmv_dtype dt);
+
+// features.hip
+void compute_features(spmv_matrix_s *h, float out[12], int32_t *hyb_width, hipStream_t s);
+
+// timing.hip
+void flush_caches(hipStream_t s);
+
+// ---- device helpers -------------------------------------------------------------
+
+constexpr int kWave = 64;
+constexpr int kNumXcd = 8;
+
+// Workgroups are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8).
+// This bijection gives each XCD one contiguous range of logical blocks, so
+// neighbouring tiles (which share x entries for banded and stencil matrices)
+// hit the same L2.
+__device__ __forceinline__ int xcd_logical_block(int b, int nb) {
+    int q = nb / kNumXcd, r = nb % kNumXcd;
+    int x = b % kNumXcd, i = b / kNumXcd;
+    return x * q + (x < r ? x : r) + i;
+}
+
+template <class T>
+__device__ __forceinline__ T ld_stream(const T *p) {
+    return __builtin_nontemporal_load(p);
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace spmv

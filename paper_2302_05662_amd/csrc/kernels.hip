@@ -1,0 +1,628 @@
+// SpMV kernels, y = alpha * A * x + beta * y, for the formats of the run-time
+// mode (paper, Background: popular SpMV formats; HYB after Bell and Garland).
+//
+// All kernels stream the matrix arrays once with non-temporal loads (so they
+// do not evict x from L2 / Infinity Cache) and gather x through the caches.
+// FP32 matrices accumulate in FP64: the FP32 products are exact in FP64, and
+// the one rounding at the end keeps long rows (50K entries) far inside a 1e-5
+// per-row error budget whatever the lane split. SpMV is memory bound, so the
+// wider accumulator costs no time.
+#include <algorithm>
+#include <climits>
+#include <vector>
+
+#include "common.hpp"
+
+namespace spmv {
+namespace {
+
+typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// ---- N consecutive elements, loaded with the widest aligned vector ----------------
+
+template <class T, int N> struct Pack { T v[N]; };
+
+template <int N>
+__device__ __forceinline__ Pack<int32_t, N> ld_i32(const int32_t *p) {
+    Pack<int32_t, N> r;
+    if constexpr (N == 1) {
+        r.v[0] = ld_stream(p);
+    } else if constexpr (N == 2) {
+        i32x2 a = __builtin_nontemporal_load((const i32x2 *)p);
+        r.v[0] = a.x; r.v[1] = a.y;
+    } else {
+        static_assert(N % 4 == 0, "");
+#pragma unroll
+        for (int q = 0; q < N; q += 4) {
+            i32x4 a = __builtin_nontemporal_load((const i32x4 *)(p + q));
+            r.v[q] = a.x; r.v[q + 1] = a.y; r.v[q + 2] = a.z; r.v[q + 3] = a.w;
+        }
+    }
+    return r;
+}
+
+template <int N>
+__device__ __forceinline__ Pack<float, N> ld_val(const float *p) {
+    Pack<float, N> r;
+    if constexpr (N == 1) {
+        r.v[0] = ld_stream(p);
+    } else if constexpr (N == 2) {
+        f32x2 a = __builtin_nontemporal_load((const f32x2 *)p);
+        r.v[0] = a.x; r.v[1] = a.y;
+    } else {
+        static_assert(N % 4 == 0, "");
+#pragma unroll
+        for (int q = 0; q < N; q += 4) {
+            f32x4 a = __builtin_nontemporal_load((const f32x4 *)(p + q));
+            r.v[q] = a.x; r.v[q + 1] = a.y; r.v[q + 2] = a.z; r.v[q + 3] = a.w;
+        }
+    }
+    return r;
+}
+
+template <int N>
+__device__ __forceinline__ Pack<double, N> ld_val(const double *p) {
+    Pack<double, N> r;
+    if constexpr (N == 1) {
+        r.v[0] = ld_stream(p);
+    } else {
+        static_assert(N % 2 == 0, "");
+#pragma unroll
+        for (int q = 0; q < N; q += 2) {
+            f64x2 a = __builtin_nontemporal_load((const f64x2 *)(p + q));
+            r.v[q] = a.x; r.v[q + 1] = a.y;
+        }
+    }
+    return r;
+}
+
+// y_i = alpha * s + beta * y_i, with y not read when beta == 0.
+template <class V>
+__device__ __forceinline__ void store_y(V *y, int64_t i, double s, V alpha, V beta) {
+    double r = (double)alpha * s;
+    if (beta != V(0)) r += (double)beta * (double)y[i];
+    y[i] = (V)r;
+}
+
+// ---- CSR scalar: one thread per row ----------------------------------------------
+
+template <class V, int BLOCK, int UNROLL>
+__global__ __launch_bounds__(BLOCK) void csr_scalar_kernel(
+    int32_t n_rows, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+    const V *__restrict__ val, const V *__restrict__ x, V alpha, V beta, V *__restrict__ y) {
+    const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int64_t i = (int64_t)b * BLOCK + threadIdx.x;
+    if (i >= n_rows) return;
+    const int32_t s = rp[i], e = rp[i + 1];
+    double acc[UNROLL];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) acc[u] = 0.0;
+    int32_t j = s;
+    for (; j + UNROLL <= e; j += UNROLL) {
+        int32_t c[UNROLL];
+        V v[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) { c[u] = ld_stream(col + j + u); v[u] = ld_stream(val + j + u); }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) acc[u] += (double)v[u] * (double)x[c[u]];
+    }
+    for (; j < e; ++j) acc[0] += (double)ld_stream(val + j) * (double)x[ld_stream(col + j)];
+    double sum = acc[0];
+#pragma unroll
+    for (int u = 1; u < UNROLL; ++u) sum += acc[u];
+    store_y(y, i, sum, alpha, beta);
+}
+
+// ---- CSR vector: L lanes of a wavefront per row ------------------------------------
+
+template <int L>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, L);
+    return v;
+}
+
+template <class V, int BLOCK, int L, int UNROLL>
+__global__ __launch_bounds__(BLOCK) void csr_vector_kernel(
+    int32_t n_rows, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+    const V *__restrict__ val, const V *__restrict__ x, V alpha, V beta, V *__restrict__ y) {
+    constexpr int RPB = BLOCK / L;  // rows per workgroup
+    __shared__ int32_t s_rp[RPB + 1];
+    const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int64_t row0 = (int64_t)b * RPB;
+    for (int t = threadIdx.x; t <= RPB; t += BLOCK)
+        s_rp[t] = rp[std::min<int64_t>(row0 + t, n_rows)];
+    __syncthreads();
+    const int g = threadIdx.x / L, lane = threadIdx.x % L;
+    const int32_t s = s_rp[g], e = s_rp[g + 1];
+    double acc = 0.0;
+    int32_t j = s + lane;
+    if constexpr (UNROLL > 1) {
+        for (; j + (UNROLL - 1) * L < e; j += UNROLL * L) {
+            int32_t c[UNROLL];
+            V v[UNROLL];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                c[u] = ld_stream(col + j + u * L);
+                v[u] = ld_stream(val + j + u * L);
+            }
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) acc += (double)v[u] * (double)x[c[u]];
+        }
+    }
+    for (; j < e; j += L) acc += (double)ld_stream(val + j) * (double)x[ld_stream(col + j)];
+    acc = group_sum<L>(acc);
+    const int64_t row = row0 + g;
+    if (lane == 0 && row < n_rows) store_y(y, row, acc, alpha, beta);
+}
+
+// ---- ELL: RPT consecutive rows per thread, column-major slots ----------------------
+
+template <class V, int BLOCK, int RPT, int UNROLL>
+__global__ __launch_bounds__(BLOCK) void ell_kernel(int32_t n_rows, int32_t K, int32_t pitch,
+                                                    const int32_t *__restrict__ ecol,
+                                                    const V *__restrict__ evals,
+                                                    const V *__restrict__ x, V alpha, V beta,
+                                                    V *__restrict__ y) {
+    const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int64_t i0 = ((int64_t)b * BLOCK + threadIdx.x) * RPT;
+    if (i0 >= n_rows) return;
+    double acc[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) acc[q] = 0.0;
+    int32_t k = 0;
+    if constexpr (UNROLL > 1) {
+        for (; k + UNROLL <= K; k += UNROLL) {
+            Pack<int32_t, RPT> c[UNROLL];
+            Pack<V, RPT> v[UNROLL];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                const int64_t off = (int64_t)(k + u) * pitch + i0;
+                c[u] = ld_i32<RPT>(ecol + off);
+                v[u] = ld_val<RPT>(evals + off);
+            }
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+                for (int q = 0; q < RPT; ++q)
+                    if (c[u].v[q] >= 0) acc[q] += (double)v[u].v[q] * (double)x[c[u].v[q]];
+        }
+    }
+    for (; k < K; ++k) {
+        const int64_t off = (int64_t)k * pitch + i0;
+        Pack<int32_t, RPT> c = ld_i32<RPT>(ecol + off);
+        Pack<V, RPT> v = ld_val<RPT>(evals + off);
+#pragma unroll
+        for (int q = 0; q < RPT; ++q)
+            if (c.v[q] >= 0) acc[q] += (double)v.v[q] * (double)x[c.v[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+        if (i0 + q < n_rows) store_y(y, i0 + q, acc[q], alpha, beta);
+}
+
+// ---- COO: nnz tiles, segmented reduction by row -------------------------------------
+//
+// Tile t holds entries [t*TILE, min(nnz, (t+1)*TILE)); thread j of the tile holds
+// ITEMS consecutive entries. A row segment that lies inside one tile is summed by a
+// block-wide segmented scan and written directly. A row that crosses a tile edge
+// leaves one partial sum per tile (slot 2t: the tile's first row, slot 2t+1: its
+// last row); coo_fixup adds them in tile order. Rows without entries are written
+// by the entry that follows the gap. ACCUM adds alpha*s to y instead (HYB tail).
+
+template <class V, int BLOCK, int ITEMS, bool ACCUM>
+__global__ __launch_bounds__(BLOCK) void coo_tile_kernel(
+    int64_t nnz, int32_t n_rows, const int32_t *__restrict__ row, const int32_t *__restrict__ col,
+    const V *__restrict__ val, const V *__restrict__ x, V alpha, V beta, V *__restrict__ y,
+    double *__restrict__ part) {
+    constexpr int TILE = BLOCK * ITEMS;
+    constexpr int WAVES = BLOCK / kWave;
+    __shared__ int32_t s_first[BLOCK + 1];
+    __shared__ int32_t s_last[BLOCK];
+    __shared__ int s_wf[WAVES];
+    __shared__ double s_ws[WAVES];
+
+    const int64_t tile = blockIdx.x;
+    const int64_t t0 = tile * TILE;
+    const int64_t t1 = std::min<int64_t>(nnz, t0 + TILE);
+    const int64_t k0 = t0 + (int64_t)threadIdx.x * ITEMS;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+
+    int32_t r[ITEMS];
+    double p[ITEMS];
+    int n_valid = 0;
+    if (k0 + ITEMS <= t1) {
+        Pack<int32_t, ITEMS> rr = ld_i32<ITEMS>(row + k0);
+        Pack<int32_t, ITEMS> cc = ld_i32<ITEMS>(col + k0);
+        Pack<V, ITEMS> vv = ld_val<ITEMS>(val + k0);
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            r[i] = rr.v[i];
+            p[i] = (double)vv.v[i] * (double)x[cc.v[i]];
+        }
+        n_valid = ITEMS;
+    } else {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const int64_t k = k0 + i;
+            if (k < t1) {
+                r[i] = ld_stream(row + k);
+                p[i] = (double)ld_stream(val + k) * (double)x[ld_stream(col + k)];
+                ++n_valid;
+            } else {
+                r[i] = INT_MAX;
+                p[i] = 0.0;
+            }
+        }
+    }
+    s_first[threadIdx.x] = r[0];
+    s_last[threadIdx.x] = n_valid ? r[n_valid - 1] : INT_MAX;
+    if (threadIdx.x == 0) s_first[BLOCK] = INT_MAX;
+    __syncthreads();
+
+    // Row of the entry before this thread's first one (tile edge counts as a head).
+    const int32_t prev_row = (threadIdx.x == 0) ? INT_MIN : s_last[threadIdx.x - 1];
+    const int32_t next_row = s_first[threadIdx.x + 1];
+
+    // Thread aggregate for the segmented scan: (a head occurred, sum since last head).
+    bool f = false;
+    double sum = 0.0;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        if (i < n_valid) {
+            const bool head = (i == 0) ? (r[0] != prev_row) : (r[i] != r[i - 1]);
+            if (head) { f = true; sum = p[i]; } else { sum += p[i]; }
+        }
+    }
+    // Inclusive segmented scan across the wave.
+    bool fi = f;
+    double si = sum;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int of = __shfl_up((int)fi, d, kWave);
+        const double os = __shfl_up(si, d, kWave);
+        if (lane >= d) {
+            if (!fi) si += os;
+            fi = fi || of;
+        }
+    }
+    if (lane == kWave - 1) { s_wf[wave] = fi; s_ws[wave] = si; }
+    // Exclusive within the wave.
+    int ef = __shfl_up((int)fi, 1, kWave);
+    double es = __shfl_up(si, 1, kWave);
+    if (lane == 0) { ef = 0; es = 0.0; }
+    __syncthreads();
+    // Prefix of the earlier waves.
+    bool wf = false;
+    double ws = 0.0;
+    for (int w = 0; w < wave; ++w) {
+        if (s_wf[w]) { wf = true; ws = s_ws[w]; } else { ws += s_ws[w]; }
+    }
+    double carry = ef ? es : ws + es;
+    (void)wf;
+
+    const int32_t r_first = row[t0];
+    const int32_t r_last = row[t1 - 1];
+    const bool open_start = t0 > 0 && row[t0 - 1] == r_first;
+    const bool open_end = t1 < nnz && row[t1] == r_last;
+
+    double acc = carry;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        if (i < n_valid) {
+            const bool head = (i == 0) ? (r[0] != prev_row) : (r[i] != r[i - 1]);
+            acc = head ? p[i] : acc + p[i];
+            const int32_t nxt = (i + 1 < n_valid) ? r[i + 1] : next_row;
+            if (nxt != r[i]) {  // segment ends here (a tile edge always ends one)
+                const bool first = open_start && r[i] == r_first;
+                const bool last = open_end && r[i] == r_last;
+                if (!first && !last) {
+                    if constexpr (ACCUM) y[r[i]] = (V)((double)y[r[i]] + (double)alpha * acc);
+                    else store_y(y, r[i], acc, alpha, beta);
+                } else {
+                    if (first) part[2 * tile] = acc;
+                    if (last) part[2 * tile + 1] = acc;
+                }
+            }
+        }
+    }
+
+    if constexpr (!ACCUM) {
+        // Empty rows: the entry after a gap writes the rows in between.
+        for (int i = 0; i < n_valid; ++i) {
+            const int64_t k = k0 + i;
+            int32_t before;
+            if (i > 0) before = r[i - 1];
+            else if (k == 0) before = -1;
+            else if (threadIdx.x > 0) before = s_last[threadIdx.x - 1];
+            else before = row[k - 1];
+            for (int32_t g = before + 1; g < r[i]; ++g) store_y(y, g, 0.0, alpha, beta);
+            if (k == nnz - 1)
+                for (int32_t g = r[i] + 1; g < n_rows; ++g) store_y(y, g, 0.0, alpha, beta);
+        }
+    }
+}
+
+template <class V, int TILE, bool ACCUM>
+__global__ __launch_bounds__(256) void coo_fixup(int64_t nnz, int64_t n_tiles,
+                                                 const int32_t *__restrict__ row,
+                                                 const double *__restrict__ part, V alpha, V beta,
+                                                 V *__restrict__ y) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n_tiles) return;
+    const int64_t t0 = t * TILE, t1 = std::min<int64_t>(nnz, t0 + TILE);
+    const int32_t r_first = row[t0], r_last = row[t1 - 1];
+    const bool open_start = t0 > 0 && row[t0 - 1] == r_first;
+    const bool open_end = t1 < nnz && row[t1] == r_last;
+    if (!open_end) return;
+    if (open_start && r_first == r_last) return;  // inside a chain, not its start
+    double s = part[2 * t + 1];
+    for (int64_t u = t + 1; u < n_tiles; ++u) {
+        s += part[2 * u];
+        const int64_t u1 = std::min<int64_t>(nnz, (u + 1) * TILE);
+        if (!(u1 < nnz && row[u1 - 1] == r_last && row[u1] == r_last)) break;
+    }
+    if constexpr (ACCUM) y[r_last] = (V)((double)y[r_last] + (double)alpha * s);
+    else store_y(y, r_last, s, alpha, beta);
+}
+
+template <class V>
+__global__ __launch_bounds__(256) void scale_y(int32_t n, V beta, V *__restrict__ y) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        y[i] = beta == V(0) ? V(0) : (V)((double)beta * (double)y[i]);
+}
+
+// ---- variant tables and launchers ------------------------------------------------
+
+struct Args {
+    const spmv_matrix_s *h;
+    const void *x;
+    void *y;
+    double alpha, beta;
+    hipStream_t s;
+};
+
+using Launcher = void (*)(const Args &);
+
+struct Variant {
+    spmv_variant_info info;
+    Launcher f32, f64;
+};
+
+inline int grid_of(int64_t units, int per_block) {
+    int64_t g = ceil_div(std::max<int64_t>(units, 1), per_block);
+    if (g > INT32_MAX) fail(SPMV_ERR_INVALID_ARG, "grid too large");
+    return (int)g;
+}
+
+template <class V>
+void launch_coo_arrays(int64_t nnz, int32_t n_rows, const int32_t *row, const int32_t *col,
+                       const V *val, const Args &a, double *part, int items, bool accum);
+
+template <class V, int ITEMS, bool ACCUM>
+void coo_launch_impl(int64_t nnz, int32_t n_rows, const int32_t *row, const int32_t *col,
+                     const V *val, const Args &a, double *part) {
+    constexpr int BLOCK = 256, TILE = BLOCK * ITEMS;
+    const V al = (V)a.alpha, be = (V)a.beta;
+    if (nnz == 0) {
+        if (!ACCUM && n_rows > 0) {
+            scale_y<V><<<std::min(grid_of(n_rows, 256), 4096), 256, 0, a.s>>>(n_rows, be, (V *)a.y);
+            SPMV_CHECK_LAUNCH();
+        }
+        return;
+    }
+    const int64_t tiles = ceil_div(nnz, TILE);
+    coo_tile_kernel<V, BLOCK, ITEMS, ACCUM><<<grid_of(nnz, TILE), BLOCK, 0, a.s>>>(
+        nnz, n_rows, row, col, val, (const V *)a.x, al, be, (V *)a.y, part);
+    SPMV_CHECK_LAUNCH();
+    if (tiles > 1) {
+        coo_fixup<V, TILE, ACCUM><<<grid_of(tiles, 256), 256, 0, a.s>>>(nnz, tiles, row, part, al,
+                                                                       be, (V *)a.y);
+        SPMV_CHECK_LAUNCH();
+    }
+}
+
+template <class V>
+void launch_coo_arrays(int64_t nnz, int32_t n_rows, const int32_t *row, const int32_t *col,
+                       const V *val, const Args &a, double *part, int items, bool accum) {
+#define COO_CASE(IT)                                                                         \
+    if (items == IT) {                                                                       \
+        if (accum) coo_launch_impl<V, IT, true>(nnz, n_rows, row, col, val, a, part);        \
+        else coo_launch_impl<V, IT, false>(nnz, n_rows, row, col, val, a, part);             \
+        return;                                                                              \
+    }
+    COO_CASE(2)
+    COO_CASE(4)
+    COO_CASE(8)
+#undef COO_CASE
+    fail(SPMV_ERR_INVALID_ARG, "bad COO items %d", items);
+}
+
+template <class V, int UNROLL>
+void csr_scalar_launch(const Args &a) {
+    const spmv_matrix_s *h = a.h;
+    if (h->n_rows == 0) return;
+    csr_scalar_kernel<V, 256, UNROLL><<<grid_of(h->n_rows, 256), 256, 0, a.s>>>(
+        h->n_rows, h->row_ptr.as<int32_t>(), h->col.as<int32_t>(), h->val.as<V>(),
+        (const V *)a.x, (V)a.alpha, (V)a.beta, (V *)a.y);
+    SPMV_CHECK_LAUNCH();
+}
+
+template <class V, int L, int UNROLL>
+void csr_vector_launch(const Args &a) {
+    const spmv_matrix_s *h = a.h;
+    if (h->n_rows == 0) return;
+    constexpr int BLOCK = 256;
+    csr_vector_kernel<V, BLOCK, L, UNROLL><<<grid_of(h->n_rows, BLOCK / L), BLOCK, 0, a.s>>>(
+        h->n_rows, h->row_ptr.as<int32_t>(), h->col.as<int32_t>(), h->val.as<V>(),
+        (const V *)a.x, (V)a.alpha, (V)a.beta, (V *)a.y);
+    SPMV_CHECK_LAUNCH();
+}
+
+template <class V, int ITEMS>
+void coo_launch(const Args &a) {
+    const spmv_matrix_s *h = a.h;
+    coo_launch_impl<V, ITEMS, false>(h->nnz, h->n_rows, h->row.as<int32_t>(), h->col.as<int32_t>(),
+                                     h->val.as<V>(), a, h->coo_partials.as<double>());
+}
+
+template <class V, int RPT, int UNROLL>
+void ell_arrays_launch(int32_t n_rows, int32_t K, int32_t pitch, const int32_t *ecol,
+                       const V *evals, const Args &a) {
+    if (n_rows == 0) return;
+    constexpr int BLOCK = 256;
+    ell_kernel<V, BLOCK, RPT, UNROLL><<<grid_of(ceil_div(n_rows, RPT), BLOCK), BLOCK, 0, a.s>>>(
+        n_rows, K, pitch, ecol, evals, (const V *)a.x, (V)a.alpha, (V)a.beta, (V *)a.y);
+    SPMV_CHECK_LAUNCH();
+}
+
+template <class V, int RPT, int UNROLL>
+void ell_launch(const Args &a) {
+    const spmv_matrix_s *h = a.h;
+    ell_arrays_launch<V, RPT, UNROLL>(h->n_rows, h->ell.K, h->ell.pitch, h->ell.col.as<int32_t>(),
+                                      h->ell.val.as<V>(), a);
+}
+
+template <class V, int RPT, int ITEMS>
+void hyb_launch(const Args &a) {
+    const spmv_matrix_s *h = a.h;
+    ell_arrays_launch<V, RPT, 1>(h->n_rows, h->hyb.K, h->hyb.pitch, h->hyb.ell_col.as<int32_t>(),
+                                 h->hyb.ell_val.as<V>(), a);
+    if (h->hyb.nnz_tail > 0)
+        coo_launch_impl<V, ITEMS, true>(h->hyb.nnz_tail, h->n_rows, h->hyb.tail_row.as<int32_t>(),
+                                        h->hyb.tail_col.as<int32_t>(), h->hyb.tail_val.as<V>(), a,
+                                        h->hyb.partials.as<double>());
+}
+
+#define V2(kind, blk, lanes, unr, fn) \
+    Variant{{kind, blk, lanes, unr}, fn<float>, fn<double>}
+
+template <class V> void csr_s1(const Args &a) { csr_scalar_launch<V, 1>(a); }
+template <class V> void csr_s4(const Args &a) { csr_scalar_launch<V, 4>(a); }
+#define CSRV(L, U) \
+    template <class V> void csr_v##L##_##U(const Args &a) { csr_vector_launch<V, L, U>(a); }
+CSRV(2, 1) CSRV(2, 2) CSRV(2, 4)
+CSRV(4, 1) CSRV(4, 2) CSRV(4, 4)
+CSRV(8, 1) CSRV(8, 2) CSRV(8, 4)
+CSRV(16, 1) CSRV(16, 2) CSRV(16, 4)
+CSRV(32, 1) CSRV(32, 2) CSRV(32, 4)
+CSRV(64, 1) CSRV(64, 2) CSRV(64, 4)
+#undef CSRV
+template <class V> void coo_2(const Args &a) { coo_launch<V, 2>(a); }
+template <class V> void coo_4(const Args &a) { coo_launch<V, 4>(a); }
+template <class V> void coo_8(const Args &a) { coo_launch<V, 8>(a); }
+template <class V> void ell_1_1(const Args &a) { ell_launch<V, 1, 1>(a); }
+template <class V> void ell_1_2(const Args &a) { ell_launch<V, 1, 2>(a); }
+template <class V> void ell_2_1(const Args &a) { ell_launch<V, 2, 1>(a); }
+template <class V> void ell_2_2(const Args &a) { ell_launch<V, 2, 2>(a); }
+template <class V> void ell_4_1(const Args &a) { ell_launch<V, 4, 1>(a); }
+template <class V> void ell_4_2(const Args &a) { ell_launch<V, 4, 2>(a); }
+template <class V> void hyb_1_4(const Args &a) { hyb_launch<V, 1, 4>(a); }
+template <class V> void hyb_1_8(const Args &a) { hyb_launch<V, 1, 8>(a); }
+template <class V> void hyb_2_4(const Args &a) { hyb_launch<V, 2, 4>(a); }
+template <class V> void hyb_2_8(const Args &a) { hyb_launch<V, 2, 8>(a); }
+
+const std::vector<Variant> &table(spmv_format f) {
+    static const std::vector<Variant> csr = {
+        V2(SPMV_KERNEL_CSR_SCALAR, 256, 1, 1, csr_s1),
+        V2(SPMV_KERNEL_CSR_SCALAR, 256, 1, 4, csr_s4),
+        V2(SPMV_KERNEL_CSR_VECTOR, 256, 2, 1, csr_v2_1),
+        V2(SPMV_KERNEL_CSR_VECTOR, 256, 2, 2, csr_v2_2),
+        V2(SPMV_KERNEL_CSR_VECTOR, 256, 2, 4, csr_v2_4),
+        V2(SPMV_KERNEL_CSR_VECTOR, 256, 4, 1, csr_v4_1),
+        V2(SPMV_KERNEL_CSR_VECTOR, 256, 4, 2, csr_v4_2),
+        V2(SPMV_KERNEL_CSR_VECTOR, 256, 4, 4, csr_v4_4),
+        V2(SPMV_KERNEL_CSR_VECTOR, 256, 8, 1, csr_v8_1),
+        V2(SPMV_KERNEL_CSR_VECTOR, 256, 8, 2, csr_v8_2),
+        V2(SPMV_KERNEL_CSR_VECTOR, 256, 8, 4, csr_v8_4),
+        V2(SPMV_KERNEL_CSR_VECTOR, 256, 16, 1, csr_v16_1),
+        V2(SPMV_KERNEL_CSR_VECTOR, 256, 16, 2, csr_v16_2),
+        V2(SPMV_KERNEL_CSR_VECTOR, 256, 16, 4, csr_v16_4),
+        V2(SPMV_KERNEL_CSR_VECTOR, 256, 32, 1, csr_v32_1),
+        V2(SPMV_KERNEL_CSR_VECTOR, 256, 32, 2, csr_v32_2),
+        V2(SPMV_KERNEL_CSR_VECTOR, 256, 32, 4, csr_v32_4),
+        V2(SPMV_KERNEL_CSR_VECTOR, 256, 64, 1, csr_v64_1),
+        V2(SPMV_KERNEL_CSR_VECTOR, 256, 64, 2, csr_v64_2),
+        V2(SPMV_KERNEL_CSR_VECTOR, 256, 64, 4, csr_v64_4),
+    };
+    static const std::vector<Variant> coo = {
+        V2(SPMV_KERNEL_COO, 256, 2, 1, coo_2),
+        V2(SPMV_KERNEL_COO, 256, 4, 1, coo_4),
+        V2(SPMV_KERNEL_COO, 256, 8, 1, coo_8),
+    };
+    static const std::vector<Variant> ell = {
+        V2(SPMV_KERNEL_ELL, 256, 1, 1, ell_1_1), V2(SPMV_KERNEL_ELL, 256, 1, 2, ell_1_2),
+        V2(SPMV_KERNEL_ELL, 256, 2, 1, ell_2_1), V2(SPMV_KERNEL_ELL, 256, 2, 2, ell_2_2),
+        V2(SPMV_KERNEL_ELL, 256, 4, 1, ell_4_1), V2(SPMV_KERNEL_ELL, 256, 4, 2, ell_4_2),
+    };
+    static const std::vector<Variant> hyb = {
+        V2(SPMV_KERNEL_HYB, 256, 1, 4, hyb_1_4), V2(SPMV_KERNEL_HYB, 256, 1, 8, hyb_1_8),
+        V2(SPMV_KERNEL_HYB, 256, 2, 4, hyb_2_4), V2(SPMV_KERNEL_HYB, 256, 2, 8, hyb_2_8),
+    };
+    static const std::vector<Variant> none;
+    switch (f) {
+        case SPMV_FMT_CSR: return csr;
+        case SPMV_FMT_COO: return coo;
+        case SPMV_FMT_ELL: return ell;
+        case SPMV_FMT_HYB: return hyb;
+    }
+    return none;
+}
+
+}  // namespace
+
+// Smallest COO tile is 256 threads x 2 entries.
+int64_t coo_partials_bytes(int64_t nnz, spmv_dtype) {
+    return 2 * std::max<int64_t>(1, ceil_div(nnz, 512)) * (int64_t)sizeof(double);
+}
+
+int32_t variant_count(spmv_format f, spmv_dtype dt) {
+    if (dt != SPMV_F32 && dt != SPMV_F64) return 0;
+    return (int32_t)table(f).size();
+}
+
+bool variant_describe(spmv_format f, spmv_dtype dt, int32_t idx, spmv_variant_info *out) {
+    const auto &t = table(f);
+    if (dt != SPMV_F32 && dt != SPMV_F64) return false;
+    if (idx < 0 || idx >= (int32_t)t.size()) return false;
+    if (out) *out = t[idx].info;
+    return true;
+}
+
+int32_t default_variant(const spmv_matrix_s *h, spmv_format f) {
+    switch (f) {
+        case SPMV_FMT_CSR: {
+            // lanes per row ~ mean row length, two loads in flight per lane
+            const double mean = h->n_rows ? (double)h->nnz / h->n_rows : 0.0;
+            int L = 2;
+            while (L < 64 && L < mean) L *= 2;
+            const auto &t = table(f);
+            for (int32_t i = 0; i < (int32_t)t.size(); ++i)
+                if (t[i].info.kernel == SPMV_KERNEL_CSR_VECTOR && t[i].info.lanes == L &&
+                    t[i].info.unroll == 2)
+                    return i;
+            return 0;
+        }
+        case SPMV_FMT_COO: return 1;
+        case SPMV_FMT_ELL: return 0;
+        case SPMV_FMT_HYB: return 0;
+    }
+    return 0;
+}
+
+void launch_spmv(const spmv_matrix_s *h, spmv_format f, int32_t variant, double alpha,
+                 const void *x, double beta, void *y, hipStream_t s) {
+    const auto &t = table(f);
+    if (variant < 0 || variant >= (int32_t)t.size())
+        fail(SPMV_ERR_INVALID_ARG, "variant %d out of range for format %d", variant, (int)f);
+    Args a{h, x, y, alpha, beta, s};
+    if (h->dt == SPMV_F64) t[variant].f64(a);
+    else t[variant].f32(a);
+}
+
+}  // namespace spmv

@@ -1,0 +1,146 @@
+// Timing harness and autotuner.
+//
+// The paper times each kernel over hundreds to thousands of repetitions and
+// averages (Experimental Setup, GPU performance monitoring), and picks compile
+// settings such as the thread-block size per matrix (Method: compile-time
+// optimisation mode). Here every variant is a compiled instance; runs are
+// bracketed by HIP events on the caller's stream, optionally after a 1 GiB
+// read sweep that evicts the L2 caches and the 256 MB Infinity Cache so the
+// matrix really streams from HBM, and the median picks the winner.
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+#include <vector>
+
+#include "common.hpp"
+
+namespace spmv {
+namespace {
+
+constexpr size_t kFlushBytes = size_t(1) << 30;
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void scrub_kernel(const f32x4 *__restrict__ buf, int64_t n,
+                                                    float *__restrict__ sink) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        acc += buf[i];
+    const float s = acc.x + acc.y + acc.z + acc.w;
+    if (s == 1234.5f) sink[threadIdx.x] = s;  // keeps the loads alive; the buffer is zero
+}
+
+struct FlushBuffers {
+    std::mutex mu;
+    DevBuf buf[64];
+    DevBuf sink[64];
+};
+
+FlushBuffers &flush_buffers() {
+    static FlushBuffers *fb = new FlushBuffers();  // lives until process exit
+    return *fb;
+}
+
+double median_of(std::vector<float> v) {
+    if (v.empty()) return INFINITY;
+    std::sort(v.begin(), v.end());
+    const size_t n = v.size();
+    return n % 2 ? v[n / 2] : 0.5 * ((double)v[n / 2 - 1] + v[n / 2]);
+}
+
+struct Events {
+    std::vector<hipEvent_t> ev;
+    explicit Events(size_t n) : ev(n, nullptr) {
+        for (auto &e : ev) SPMV_HIP(hipEventCreate(&e));
+    }
+    ~Events() {
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+}  // namespace
+
+void flush_caches(hipStream_t s) {
+    int dev = 0;
+    SPMV_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) fail(SPMV_ERR_INVALID_ARG, "device id %d", dev);
+    FlushBuffers &fb = flush_buffers();
+    const f32x4 *p;
+    float *sink;
+    {
+        std::lock_guard<std::mutex> lk(fb.mu);
+        if (!fb.buf[dev].p) {
+            fb.buf[dev].alloc(kFlushBytes);
+            fb.sink[dev].alloc(256 * sizeof(float));
+            SPMV_HIP(hipMemset(fb.buf[dev].p, 0, kFlushBytes));
+        }
+        p = fb.buf[dev].as<const f32x4>();
+        sink = fb.sink[dev].as<float>();
+    }
+    scrub_kernel<<<4096, 256, 0, s>>>(p, (int64_t)(kFlushBytes / sizeof(f32x4)), sink);
+    SPMV_CHECK_LAUNCH();
+}
+
+void check_runnable(const spmv_matrix_s *h, spmv_format f);  // api.hip
+
+std::vector<float> time_runs(spmv_matrix_s *h, spmv_format f, int32_t variant, const void *x,
+                             void *y, int32_t warmup, int32_t reps, int flush, hipStream_t s) {
+    for (int i = 0; i < warmup; ++i) launch_spmv(h, f, variant, 1.0, x, 0.0, y, s);
+    Events e(2 * (size_t)reps);
+    for (int i = 0; i < reps; ++i) {
+        if (flush) flush_caches(s);
+        SPMV_HIP(hipEventRecord(e.ev[2 * i], s));
+        launch_spmv(h, f, variant, 1.0, x, 0.0, y, s);
+        SPMV_HIP(hipEventRecord(e.ev[2 * i + 1], s));
+    }
+    SPMV_HIP(hipStreamSynchronize(s));
+    std::vector<float> ms(reps);
+    for (int i = 0; i < reps; ++i) SPMV_HIP(hipEventElapsedTime(&ms[i], e.ev[2 * i], e.ev[2 * i + 1]));
+    return ms;
+}
+
+// Time every variant of f; make the fastest median current. Returns its median.
+double tune_format(spmv_matrix_s *h, spmv_format f, const void *x, void *y, int32_t reps, int flush,
+                   int32_t *best_idx, hipStream_t s) {
+    const int32_t nv = variant_count(f, h->dt);
+    double best = INFINITY;
+    int32_t bi = h->variant[f];
+    for (int32_t v = 0; v < nv; ++v) {
+        const double m = median_of(time_runs(h, f, v, x, y, 2, reps, flush, s));
+        if (m < best) { best = m; bi = v; }
+    }
+    h->variant[f] = bi;
+    if (best_idx) *best_idx = bi;
+    return best;
+}
+
+}  // namespace spmv
+
+using namespace spmv;
+
+extern "C" spmv_status spmv_time(spmv_handle h, spmv_format f, int32_t variant, const void *x,
+                                 void *y, int32_t warmup, int32_t reps, int flush, float *out_ms,
+                                 void *stream) {
+    return guard([&] {
+        check_runnable(h, f);
+        if (warmup < 0 || reps < 0 || (reps > 0 && !out_ms))
+            fail(SPMV_ERR_INVALID_ARG, "bad warmup/reps/out_ms");
+        if ((h->n_cols > 0 && !x) || (h->n_rows > 0 && !y)) fail(SPMV_ERR_INVALID_ARG, "NULL x or y");
+        const int32_t v = variant < 0 ? h->variant[f] : variant;
+        if (v >= variant_count(f, h->dt)) fail(SPMV_ERR_INVALID_ARG, "variant %d out of range", v);
+        std::vector<float> ms = time_runs(h, f, v, x, y, warmup, reps, flush, (hipStream_t)stream);
+        std::copy(ms.begin(), ms.end(), out_ms);
+    });
+}
+
+extern "C" spmv_status spmv_tune(spmv_handle h, spmv_format f, const void *x, void *y, int32_t reps,
+                                 int flush, int32_t *best_idx, float *best_ms, void *stream) {
+    return guard([&] {
+        check_runnable(h, f);
+        if (reps <= 0) fail(SPMV_ERR_INVALID_ARG, "reps must be positive");
+        if ((h->n_cols > 0 && !x) || (h->n_rows > 0 && !y)) fail(SPMV_ERR_INVALID_ARG, "NULL x or y");
+        const double m = tune_format(h, f, x, y, reps, flush, best_idx, (hipStream_t)stream);
+        if (best_ms) *best_ms = (float)m;
+    });
+}

@@ -1,0 +1,313 @@
+"""ctypes binding of libspmv.so (include/spmv.h), with the same function names.
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels. Torch tensors supply device memory and ``torch.cuda`` streams; host
+inputs may also be NumPy arrays. The library must have been built
+(``paper_2302_05662_amd.build.build()``); importing this module without it
+raises ImportError rather than falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libspmv.so")
+HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "spmv.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_2302_05662_amd.build.build()")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---- enums (mirror include/spmv.h) -------------------------------------------------
+
+SPMV_OK = 0
+STATUS_NAMES = ("OK", "INVALID_ARG", "OUT_OF_BOUNDS", "DUPLICATE", "NOT_CONVERTED",
+                "NOT_APPLICABLE", "OOM", "HIP", "NO_MODEL")
+SPMV_FMT_CSR, SPMV_FMT_COO, SPMV_FMT_ELL, SPMV_FMT_HYB = 0, 1, 2, 3
+FORMAT_NAMES = ("CSR", "COO", "ELL", "HYB")
+SPMV_F32, SPMV_F64 = 0, 1
+KERNEL_NAMES = ("csr_scalar", "csr_vector", "coo", "ell", "hyb")
+SPMV_SELECT_MODEL, SPMV_SELECT_EXHAUSTIVE, SPMV_SELECT_RULE = 0, 1, 2
+
+
+class SpmvError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        msg = _lib.spmv_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {name}: {msg}")
+        self.status = name
+        self.code = status
+
+
+class spmv_variant_info(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("lanes", ctypes.c_int32), ("unroll", ctypes.c_int32)]
+
+
+class spmv_arrays(ctypes.Structure):
+    _fields_ = [("format", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("n_rows", ctypes.c_int32), ("n_cols", ctypes.c_int32),
+                ("nnz", ctypes.c_int64), ("K", ctypes.c_int32), ("pitch", ctypes.c_int32),
+                ("nnz_tail", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("row", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("val", ctypes.c_void_p), ("ell_col", ctypes.c_void_p),
+                ("ell_val", ctypes.c_void_p), ("tail_row", ctypes.c_void_p),
+                ("tail_col", ctypes.c_void_p), ("tail_val", ctypes.c_void_p)]
+
+
+_P = ctypes.c_void_p
+_I32, _I64, _D, _F = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_float
+
+
+def _sig(name, res, *args):
+    fn = getattr(_lib, name)
+    fn.restype = res
+    fn.argtypes = list(args)
+    return fn
+
+
+_sig("spmv_create", _I32, ctypes.POINTER(_P), _I32, _I32, _I64, _P, _P, _P, _I32, ctypes.c_int, _P)
+_sig("spmv_destroy", None, _P)
+_sig("spmv_convert", _I32, _P, _I32, _I32, _P)
+_sig("spmv_run", _I32, _P, _I32, _D, _P, _D, _P, _P)
+_sig("spmv_get_arrays", _I32, _P, _I32, ctypes.POINTER(spmv_arrays))
+_sig("spmv_variant_count", _I32, _I32, _I32)
+_sig("spmv_variant_describe", _I32, _I32, _I32, _I32, ctypes.POINTER(spmv_variant_info))
+_sig("spmv_set_variant", _I32, _P, _I32, _I32)
+_sig("spmv_get_variant", _I32, _P, _I32, ctypes.POINTER(_I32))
+_sig("spmv_time", _I32, _P, _I32, _I32, _P, _P, _I32, _I32, ctypes.c_int, _P, _P)
+_sig("spmv_tune", _I32, _P, _I32, _P, _P, _I32, ctypes.c_int, ctypes.POINTER(_I32),
+     ctypes.POINTER(_F), _P)
+_sig("spmv_features", _I32, _P, _P, _P)
+_sig("spmv_select_format", _I32, _P, _I32, ctypes.POINTER(_I32), _P, _P)
+_sig("spmv_status_string", ctypes.c_char_p, _I32)
+_sig("spmv_last_error", ctypes.c_char_p)
+
+
+def _check(st: int, where: str):
+    if st != SPMV_OK:
+        raise SpmvError(st, where)
+
+
+def declared_functions() -> list:
+    """Names of the functions include/spmv.h declares."""
+    with open(HEADER_PATH) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(spmv_[a-z0-9_]+)\s*\(", text)))
+
+
+# ---- marshalling helpers ---------------------------------------------------------------
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        return ctypes.c_void_p(0)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dtype_code(dtype) -> int:
+    name = str(dtype)
+    if name.endswith("float32"):
+        return SPMV_F32
+    if name.endswith("float64"):
+        return SPMV_F64
+    raise ValueError(f"unsupported value dtype {dtype}")
+
+
+def _buffer(a, want_dtype=None):
+    """(pointer, on_device, keepalive) for a torch tensor or NumPy array."""
+    try:
+        import torch
+    except ImportError:  # pragma: no cover
+        torch = None
+    if torch is not None and isinstance(a, torch.Tensor):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return ctypes.c_void_p(a.data_ptr() if a.numel() else 0), a.is_cuda, a
+    arr = np.ascontiguousarray(a, dtype=want_dtype) if want_dtype is not None else np.ascontiguousarray(a)
+    return ctypes.c_void_p(arr.ctypes.data if arr.size else 0), False, arr
+
+
+class Handle:
+    """Owns one spmv_handle; destroyed by spmv_destroy (or when collected)."""
+
+    def __init__(self, ptr, n_rows, n_cols, nnz, dtype_code):
+        self.ptr = ptr
+        self.n_rows, self.n_cols, self.nnz = n_rows, n_cols, nnz
+        self.dtype_code = dtype_code
+
+    @property
+    def value_dtype(self):
+        return np.float64 if self.dtype_code == SPMV_F64 else np.float32
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            _lib.spmv_destroy(self.ptr)
+            self.ptr = None
+
+
+# ---- the ABI, one wrapper per function ----------------------------------------------
+
+def spmv_create(n_rows, n_cols, row, col, val, stream=None) -> Handle:
+    """COO (any order) -> handle with canonical COO/CSR on the device."""
+    dt = _dtype_code(val.dtype)
+    pr, dr, kr = _buffer(row, np.int32)
+    pc, dc, kc = _buffer(col, np.int32)
+    pv, dv, kv = _buffer(val)
+    if not (dr == dc == dv):
+        raise ValueError("row, col and val must all be on the host or all on the device")
+    nnz = int(kr.shape[0])
+    out = ctypes.c_void_p()
+    _check(_lib.spmv_create(ctypes.byref(out), int(n_rows), int(n_cols), nnz, pr, pc, pv, dt,
+                            int(dr), _stream_ptr(stream)), "spmv_create")
+    return Handle(out, int(n_rows), int(n_cols), nnz, dt)
+
+
+def spmv_destroy(h: Handle):
+    if h.ptr:
+        _lib.spmv_destroy(h.ptr)
+        h.ptr = None
+
+
+def spmv_convert(h: Handle, fmt: int, hyb_k: int = -1, stream=None):
+    _check(_lib.spmv_convert(h.ptr, int(fmt), int(hyb_k), _stream_ptr(stream)), "spmv_convert")
+
+
+def _device_buffer(a, name):
+    p, on_dev, _ = _buffer(a)
+    if not on_dev and p.value:
+        raise ValueError(f"{name} must be a device tensor")
+    return p
+
+
+def spmv_run(h: Handle, fmt: int, alpha, x, beta, y, stream=None):
+    """y = alpha * A x + beta * y on the device (x, y: device tensors)."""
+    px = _device_buffer(x, "x")
+    py = _device_buffer(y, "y")
+    _check(_lib.spmv_run(h.ptr, int(fmt), float(alpha), px, float(beta), py, _stream_ptr(stream)),
+           "spmv_run")
+
+
+def spmv_get_arrays(h: Handle, fmt: int) -> spmv_arrays:
+    v = spmv_arrays()
+    _check(_lib.spmv_get_arrays(h.ptr, int(fmt), ctypes.byref(v)), "spmv_get_arrays")
+    return v
+
+
+def spmv_variant_count(fmt: int, dtype_code: int) -> int:
+    return int(_lib.spmv_variant_count(int(fmt), int(dtype_code)))
+
+
+def spmv_variant_describe(fmt: int, dtype_code: int, idx: int) -> dict:
+    v = spmv_variant_info()
+    _check(_lib.spmv_variant_describe(int(fmt), int(dtype_code), int(idx), ctypes.byref(v)),
+           "spmv_variant_describe")
+    return {"kernel": KERNEL_NAMES[v.kernel], "block": v.block, "lanes": v.lanes,
+            "unroll": v.unroll}
+
+
+def spmv_set_variant(h: Handle, fmt: int, idx: int):
+    _check(_lib.spmv_set_variant(h.ptr, int(fmt), int(idx)), "spmv_set_variant")
+
+
+def spmv_get_variant(h: Handle, fmt: int) -> int:
+    out = _I32()
+    _check(_lib.spmv_get_variant(h.ptr, int(fmt), ctypes.byref(out)), "spmv_get_variant")
+    return int(out.value)
+
+
+def spmv_time(h: Handle, fmt: int, x, y, variant=-1, warmup=2, reps=10, flush=True,
+              stream=None) -> np.ndarray:
+    out = np.zeros(max(int(reps), 0), dtype=np.float32)
+    px = _device_buffer(x, "x")
+    py = _device_buffer(y, "y")
+    _check(_lib.spmv_time(h.ptr, int(fmt), int(variant), px, py, int(warmup), int(reps),
+                          int(bool(flush)), ctypes.c_void_p(out.ctypes.data if out.size else 0),
+                          _stream_ptr(stream)), "spmv_time")
+    return out
+
+
+def spmv_tune(h: Handle, fmt: int, x, y, reps=10, flush=True, stream=None):
+    """Time every variant of fmt, keep the fastest; returns (variant, median ms)."""
+    px = _device_buffer(x, "x")
+    py = _device_buffer(y, "y")
+    bi, bm = _I32(), _F()
+    _check(_lib.spmv_tune(h.ptr, int(fmt), px, py, int(reps), int(bool(flush)), ctypes.byref(bi),
+                          ctypes.byref(bm), _stream_ptr(stream)), "spmv_tune")
+    return int(bi.value), float(bm.value)
+
+
+def spmv_features(h: Handle, stream=None) -> np.ndarray:
+    out = np.zeros(12, dtype=np.float32)
+    _check(_lib.spmv_features(h.ptr, ctypes.c_void_p(out.ctypes.data), _stream_ptr(stream)),
+           "spmv_features")
+    return out
+
+
+def spmv_select_format(h: Handle, mode: int, stream=None):
+    """(format, scores[4]) chosen by MODEL / EXHAUSTIVE / RULE."""
+    f = _I32()
+    scores = np.zeros(4, dtype=np.float32)
+    _check(_lib.spmv_select_format(h.ptr, int(mode), ctypes.byref(f),
+                                   ctypes.c_void_p(scores.ctypes.data), _stream_ptr(stream)),
+           "spmv_select_format")
+    return int(f.value), scores
+
+
+def spmv_status_string(status: int) -> str:
+    return _lib.spmv_status_string(int(status)).decode()
+
+
+def spmv_last_error() -> str:
+    return _lib.spmv_last_error().decode(errors="replace")
+
+
+# ---- device-array views -------------------------------------------------------------------
+
+class _DeviceView:
+    def __init__(self, ptr, n, typestr):
+        self.__cuda_array_interface__ = {"shape": (int(n),), "typestr": typestr,
+                                         "data": (int(ptr or 0), True), "version": 2}
+
+
+def device_tensor(ptr, n, np_dtype):
+    """A torch tensor aliasing n elements of library-owned device memory (borrowed)."""
+    import torch
+    if n == 0 or not ptr:
+        return torch.zeros(0, dtype=torch.from_numpy(np.zeros(0, np_dtype)).dtype, device="cuda")
+    return torch.as_tensor(_DeviceView(ptr, n, np.dtype(np_dtype).str), device="cuda")
+
+
+def arrays_to_host(h: Handle, fmt: int) -> dict:
+    """Copy every device array of a format to NumPy (for checks)."""
+    v = spmv_get_arrays(h, fmt)
+    vd = h.value_dtype
+    out = {"K": v.K, "pitch": v.pitch, "nnz_tail": v.nnz_tail}
+    if fmt == SPMV_FMT_CSR:
+        out["row_ptr"] = device_tensor(v.row_ptr, h.n_rows + 1, np.int32).cpu().numpy()
+        out["col"] = device_tensor(v.col, h.nnz, np.int32).cpu().numpy()
+        out["val"] = device_tensor(v.val, h.nnz, vd).cpu().numpy()
+    elif fmt == SPMV_FMT_COO:
+        out["row"] = device_tensor(v.row, h.nnz, np.int32).cpu().numpy()
+        out["col"] = device_tensor(v.col, h.nnz, np.int32).cpu().numpy()
+        out["val"] = device_tensor(v.val, h.nnz, vd).cpu().numpy()
+    else:
+        n = v.K * v.pitch
+        out["ell_col"] = device_tensor(v.ell_col, n, np.int32).cpu().numpy()
+        out["ell_val"] = device_tensor(v.ell_val, n, vd).cpu().numpy()
+        if fmt == SPMV_FMT_HYB:
+            t = v.nnz_tail
+            out["tail_row"] = device_tensor(v.tail_row, t, np.int32).cpu().numpy()
+            out["tail_col"] = device_tensor(v.tail_col, t, np.int32).cpu().numpy()
+            out["tail_val"] = device_tensor(v.tail_val, t, vd).cpu().numpy()
+    return out

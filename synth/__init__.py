@@ -22,5 +22,7 @@ from .matrices import (  # noqa: F401
     config5_specs,
     config5_matrix,
     uniform_vector,
+    random_rect,
+    from_coords,
 )
 from .mlp_inputs import glorot_params, epoch_permutations  # noqa: F401

@@ -343,3 +343,19 @@ def config5_specs(seeds, n_lo: float = 4096, n_hi: float = 2e6, nnz_cap: int = C
 
 def config5_matrix(spec: dict) -> Matrix:
     return _from_spec(spec)
+
+
+def random_rect(n_rows: int, n_cols: int, nnz: int, seed: int) -> Matrix:
+    """nnz distinct uniformly placed entries of an n_rows x n_cols matrix."""
+    rng = np.random.default_rng([seed, 0])
+    flat = np.sort(rng.choice(n_rows * n_cols, nnz, replace=False))
+    row, col = np.divmod(flat, n_cols)
+    return _pack(f"rect_{n_rows}x{n_cols}_{nnz}", "rect", n_rows, n_cols, row, col, seed, {})
+
+
+def from_coords(name: str, n_rows: int, n_cols: int, row, col, seed: int = 0) -> Matrix:
+    """A matrix with the given distinct coordinates (sorted here), uniform values."""
+    row = np.asarray(row, np.int64)
+    col = np.asarray(col, np.int64)
+    o = np.lexsort((col, row))
+    return _pack(name, "custom", n_rows, n_cols, row[o], col[o], seed, {})

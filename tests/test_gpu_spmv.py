@@ -1,0 +1,156 @@
+"""GPU SpMV parity: every format, every compiled variant, FP32 and FP64, against the oracle.
+
+The bar is the per-row error |y - y_ref| / (|alpha| sum_j |a_ij x_j| + |beta y_i|):
+at most 1e-5 for FP32 and 1e-12 for FP64, with exact equality where the
+denominator is 0. Integer-valued problems must match bit for bit.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import _cases as C
+import synth
+from oracle import formats as OF
+from oracle import spmv as OS
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2302_05662_amd as S  # noqa: E402
+
+DTYPES = [np.float32, np.float64]
+FORMATS = [S.SPMV_FMT_CSR, S.SPMV_FMT_COO, S.SPMV_FMT_ELL, S.SPMV_FMT_HYB]
+
+
+def _create(name, dtype):
+    m = C.matrix(name)
+    r, c, v = C.shuffled_input(name, dtype)
+    return S.spmv_create(m.n_rows, m.n_cols, r, c, v)
+
+
+def _formats_for(h, name, dtype):
+    out = [S.SPMV_FMT_CSR, S.SPMV_FMT_COO]
+    try:
+        OF.to_ell(C.canonical(name, dtype))
+        S.spmv_convert(h, S.SPMV_FMT_ELL)
+        out.append(S.SPMV_FMT_ELL)
+    except OF.OracleError:
+        pass
+    S.spmv_convert(h, S.SPMV_FMT_HYB)
+    out.append(S.SPMV_FMT_HYB)
+    return out
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("name", list(C.CASES))
+def test_every_variant_matches_oracle(name, dtype):
+    print(f"[spmv] {name} {dtype.__name__}", flush=True)
+    m = C.matrix(name)
+    h = _create(name, dtype)
+    x, y0 = C.vectors(name, dtype)
+    xd = torch.from_numpy(x).cuda()
+    runs = []
+    for fmt in _formats_for(h, name, dtype):
+        for var in range(S.spmv_variant_count(fmt, h.dtype_code)):
+            S.spmv_set_variant(h, fmt, var)
+            for a, b in C.ALPHA_BETA:
+                yd = torch.from_numpy(y0.copy()).cuda()
+                S.spmv_run(h, fmt, a, xd, b, yd)
+                runs.append((fmt, var, a, b, yd))
+    torch.cuda.synchronize()
+    tol = C.TOL[dtype]
+    for fmt, var, a, b, yd in runs:
+        y_ref, den = C.reference(name, dtype, a, b)
+        err = OS.max_row_error(yd.cpu().numpy(), y_ref, den)
+        assert err <= tol, (S.FORMAT_NAMES[fmt], S.spmv_variant_describe(fmt, h.dtype_code, var), a, b, err)
+    assert m.n_rows == 0 or runs
+
+
+def test_laplacian_integer_closed_form_bit_exact():
+    """x = i^2 + j^2 on the 64 x 64 grid: A x = -4 + sum of x over missing neighbours."""
+    g = 64
+    m = C.matrix("lap64")
+    h = _create("lap64", np.float32)
+    i, j = np.divmod(np.arange(g * g), g)
+    x = (i * i + j * j).astype(np.float32)
+    want = []
+    for a, b in zip(i.tolist(), j.tolist()):
+        s = -4
+        for p, q in ((a - 1, b), (a + 1, b), (a, b - 1), (a, b + 1)):
+            if not (0 <= p < g and 0 <= q < g):
+                s += p * p + q * q
+        want.append(s)
+    want = np.array(want, np.float32)
+    xd = torch.from_numpy(x).cuda()
+    for fmt in _formats_for(h, "lap64", np.float32):
+        for var in range(S.spmv_variant_count(fmt, S.SPMV_F32)):
+            S.spmv_set_variant(h, fmt, var)
+            yd = torch.empty(m.n_rows, device="cuda")
+            S.spmv_run(h, fmt, 1.0, xd, 0.0, yd)
+            assert np.array_equal(yd.cpu().numpy(), want), (S.FORMAT_NAMES[fmt], var)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_beta_zero_ignores_nan_and_runs_are_deterministic(dtype):
+    name = "powerlaw"
+    m = C.matrix(name)
+    h = _create(name, dtype)
+    x, _ = C.vectors(name, dtype)
+    xd = torch.from_numpy(x).cuda()
+    y_ref, den = C.reference(name, dtype, 1.0, 0.0)
+    for fmt in _formats_for(h, name, dtype):
+        for var in range(S.spmv_variant_count(fmt, h.dtype_code)):
+            S.spmv_set_variant(h, fmt, var)
+            y1 = torch.full((m.n_rows,), float("nan"), dtype=xd.dtype, device="cuda")
+            y2 = torch.full((m.n_rows,), float("inf"), dtype=xd.dtype, device="cuda")
+            S.spmv_run(h, fmt, 1.0, xd, 0.0, y1)
+            S.spmv_run(h, fmt, 1.0, xd, 0.0, y2)
+            a, b = y1.cpu().numpy(), y2.cpu().numpy()
+            assert a.tobytes() == b.tobytes()
+            assert OS.max_row_error(a, y_ref, den) <= C.TOL[dtype]
+
+
+def _sample_rows(row_ptr, n, seed, k=3000):
+    lengths = np.diff(row_ptr)
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(n, min(k, n), replace=False)
+    longest = np.argsort(lengths)[-50:]
+    return np.unique(np.concatenate([pick, longest, [0, n - 1]]))
+
+
+@pytest.mark.parametrize("which", ["powerlaw_2M_f32", "random_f64"])
+def test_full_size_sampled_rows(which):
+    """Full-size matrices, all variants, checked on sampled rows (incl. the longest)."""
+    if which == "powerlaw_2M_f32":
+        m, dtype = synth.config3_matrix(), np.float32
+    else:
+        m, dtype = synth.config2_matrix(2009), np.float64
+    print(f"[spmv full] {m.name} nnz={m.nnz} {dtype.__name__}", flush=True)
+    v = m.values(dtype)
+    x = m.x(dtype)
+    y0 = synth.uniform_vector(m.n_rows, dtype, [m.seed, 4])
+    h = S.spmv_create(m.n_rows, m.n_cols, m.row, m.col, v)
+    row_ptr = np.zeros(m.n_rows + 1, np.int64)
+    np.cumsum(np.bincount(m.row, minlength=m.n_rows), out=row_ptr[1:])
+    rows = _sample_rows(row_ptr, m.n_rows, 7)
+    a, b = 1.5, -0.5
+    y_ref, den = OS.spmv_rows(rows, row_ptr, m.col, v, x, a, b, y0)
+    xd = torch.from_numpy(x).cuda()
+    fmts = [S.SPMV_FMT_CSR, S.SPMV_FMT_COO, S.SPMV_FMT_HYB]
+    try:
+        S.spmv_convert(h, S.SPMV_FMT_ELL)
+        fmts.append(S.SPMV_FMT_ELL)
+    except S.SpmvError as e:
+        assert e.status == "NOT_APPLICABLE"
+    S.spmv_convert(h, S.SPMV_FMT_HYB)
+    rows_t = torch.from_numpy(rows).cuda()
+    for fmt in fmts:
+        for var in range(S.spmv_variant_count(fmt, h.dtype_code)):
+            S.spmv_set_variant(h, fmt, var)
+            yd = torch.from_numpy(y0).cuda()
+            S.spmv_run(h, fmt, a, xd, b, yd)
+            got = yd[rows_t].cpu().numpy()
+            err = OS.max_row_error(got, y_ref, den)
+            assert err <= C.TOL[dtype], (S.FORMAT_NAMES[fmt], var, err)
+            assert math.isfinite(err)
