@@ -21,6 +21,11 @@ HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "spmv.h")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with paper_2302_05662_amd.build.build()")
 
+# torch ships its own HIP runtime under the same soname (libamdhip64.so.7) as
+# /opt/rocm's. Loading torch first makes that one runtime serve the whole
+# process, so torch tensors, streams and the library share one device context.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 # ---- enums (mirror include/spmv.h) -------------------------------------------------
@@ -277,7 +282,7 @@ def spmv_last_error() -> str:
 class _DeviceView:
     def __init__(self, ptr, n, typestr):
         self.__cuda_array_interface__ = {"shape": (int(n),), "typestr": typestr,
-                                         "data": (int(ptr or 0), True), "version": 2}
+                                         "data": (int(ptr or 0), False), "version": 2}
 
 
 def device_tensor(ptr, n, np_dtype):
