@@ -63,7 +63,47 @@ def load_traffic(kernel_key):
         d = json.load(fh)
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return d.get("kernels", {}).get(kernel_key)
+    t = d.get("kernels", {}).get(kernel_key)
+    return float(t) if t is not None else None
+
+
+def kernel_symbols(fmt, info, dtype="float"):
+    """Substrings of the HIP kernel names one spmv_run of (fmt, variant) launches, main kernel first."""
+    b, l, u, v = info["block"], info["lanes"], info["unroll"], info["vec"]
+    if info["kernel"] == "csr_scalar":
+        return [f"csr_scalar_kernel<{dtype}, {b}, {u}>"]
+    if info["kernel"] == "csr_vector":
+        name = "csr_vector4_kernel" if v == 4 else "csr_vector_kernel"
+        return [f"{name}<{dtype}, {b}, {l}, {u}>"]
+    if info["kernel"] == "coo":
+        return [f"coo_tile_kernel<{dtype}, {b}, {l}, false>", f"coo_fixup<{dtype}, {b * l}, false>"]
+    if info["kernel"] == "ell":
+        return [f"ell_kernel<{dtype}, {b}, {l}, {u}>"]
+    return [f"ell_kernel<{dtype}, {b}, {l}, 1>", f"coo_tile_kernel<{dtype}, {b}, {u}, true>",
+            f"coo_fixup<{dtype}, {b * u}, true>"]
+
+
+def trace_summary(trace_csv, bench_json):
+    """Average duration of the roofline kernel over the timed launches, from a rocprofv3 kernel trace."""
+    import csv
+
+    with open(bench_json) as fh:
+        line = [l for l in fh if l.startswith("{")][-1]
+    rf = json.loads(line)["roofline"]
+    sym, n = rf["kernel_symbol"], rf["launches"]
+    with open(trace_csv) as fh:
+        rows = [r for r in csv.DictReader(fh) if sym in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    timed = rows[-n:]
+    dur_us = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in timed]
+    avg = sum(dur_us) / len(dur_us)
+    print(f"kernel: {sym}")
+    print(f"dispatches in trace: {len(rows)}; timed-region dispatches used: {len(timed)}")
+    print(f"rocprofv3 average duration over the timed launches: {avg:.3f} us")
+    print(f"bench HIP-event average per launch: {rf['avg_launch_us']:.3f} us")
+    print(f"algorithmic bytes per launch (mean): {rf['bytes_per_launch']:.0f}")
+    print(f"achieved from rocprofv3 duration: {rf['bytes_per_launch'] / avg / 1e3:.1f} GB/s "
+          f"(bench: {rf['achieved']} GB/s)")
 
 
 def cpu_baseline(mats, budget_s, threads):
@@ -106,7 +146,16 @@ def main():
     ap.add_argument("--tune-reps", type=int, default=5)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle CPU work")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--plan", help="JSON of a previous run: reuse its format/variant per matrix "
+                    "instead of tuning")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the timed steps, copy MIB MiB three times (counter calibration)")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("KERNEL_TRACE_CSV", "BENCH_JSON"),
+                    help="summarise a rocprofv3 kernel trace of a previous run and exit")
     args = ap.parse_args()
+    if args.trace_summary:
+        trace_summary(*args.trace_summary)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
               "(the multi-GPU design is described, not run)", file=sys.stderr)
@@ -120,6 +169,12 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     seeds = list(synth.matrices.CFG2_SEEDS)[: args.matrices]
+
+    plan = None
+    if args.plan:
+        with open(args.plan) as fh:
+            line = [l for l in fh if l.startswith("{")][-1]
+        plan = {p["name"]: p for p in json.loads(line)["plan"]}
 
     mats = []
     t_setup = time.perf_counter()
@@ -146,9 +201,17 @@ def main():
                 continue
             entry["bytes"][fmt] = format_bytes(fmt, m.n_rows, m.n_cols, m.nnz, 4, view.K, view.pitch,
                                                view.nnz_tail)
+            if plan is not None:
+                pm = plan[m.name]
+                entry["times"][fmt] = pm["times"][fmt] if pm["times"][fmt] is not None else float("inf")
+                entry["variant"][fmt] = pm["variants"][fmt]
+                S.spmv_set_variant(h, fmt, pm["variants"][fmt])
+                continue
             var, ms = S.spmv_tune(h, fmt, xd, yd, reps=args.tune_reps, flush=True)
             entry["times"][fmt] = ms
             entry["variant"][fmt] = var
+        for fmt in range(4):
+            entry["variant"].setdefault(fmt, -1)
         entry["fmt"] = int(np.argmin([entry["times"][f] for f in range(4)]))
         entry["useful_bytes"] = entry["bytes"][0]
         if not args.no_cpu:
@@ -181,6 +244,13 @@ def main():
             per_launch[i][1] += 1
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    if args.copy_calibration:
+        src = torch.zeros(args.copy_calibration * 2**18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ms_per_step = wall * 1e3 / args.steps
     kernel_ms_per_step = sum(p[0] for p in per_launch) / args.steps
 
@@ -191,8 +261,10 @@ def main():
     groups = {}
     for e, (ms, cnt) in zip(mats, per_launch):
         info = S.spmv_variant_describe(e["fmt"], S.SPMV_F32, e["variant"][e["fmt"]])
-        key = f"{info['kernel']}_b{info['block']}_l{info['lanes']}_u{info['unroll']}_f32"
-        g = groups.setdefault(key, {"ms": 0.0, "launches": 0, "bytes": 0.0})
+        key = (f"{info['kernel']}_b{info['block']}_l{info['lanes']}_u{info['unroll']}"
+               f"_v{info['vec']}_f32")
+        g = groups.setdefault(key, {"ms": 0.0, "launches": 0, "bytes": 0.0,
+                                    "symbols": kernel_symbols(e["fmt"], info)})
         g["ms"] += ms
         g["launches"] += cnt
         g["bytes"] += e["bytes"][e["fmt"]] * cnt
@@ -259,11 +331,20 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": traffic,
             "share_of_kernel_time": round(dom["ms"] / sum(g["ms"] for g in groups.values()), 3),
+            "kernel_symbol": dom["symbols"][0],
+            "kernels_per_launch": len(dom["symbols"]),
+            "launches": dom["launches"],
+            "avg_launch_us": round(dom["ms"] * 1e3 / dom["launches"], 3),
+            "bytes_per_launch": round(dom["bytes"] / dom["launches"], 1),
         },
         "cpu_baseline": cpu,
         "per_format_tuned_cold": per_format,
         "selected_formats": chosen,
         "setup_s": round(setup_s, 1),
+        "plan": [{"name": e["name"], "fmt": e["fmt"],
+                  "variants": [e["variant"][f] for f in range(4)],
+                  "times": [e["times"][f] if np.isfinite(e["times"][f]) else None
+                            for f in range(4)]} for e in mats],
     }
     print(json.dumps(out), flush=True)
 

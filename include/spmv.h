@@ -78,6 +78,7 @@ typedef struct spmv_variant_info {
     int32_t lanes;  /* CSR vector: lanes per row; ELL/HYB: rows per thread;
                        COO: entries per thread; CSR scalar: 1                      */
     int32_t unroll; /* independent loads in flight per lane                        */
+    int32_t vec;    /* consecutive entries each lane reads with one load (1 or 4)  */
 } spmv_variant_info;
 
 /* Borrowed view of a format's device arrays; valid until spmv_destroy or a

@@ -129,9 +129,15 @@ void build_hyb(spmv_matrix_s *h, int32_t hyb_k, hipStream_t s) {
     SPMV_HIP(hipStreamSynchronize(s));
     p.nnz_tail = total;
     const size_t vs = dtype_size(h->dt);
-    p.tail_row.alloc((int64_t)total * 4);
-    p.tail_col.alloc((int64_t)total * 4);
-    p.tail_val.alloc((int64_t)total * vs);
+    const int64_t tp = padded_count(total);
+    p.tail_row.alloc(tp * 4);
+    p.tail_col.alloc(tp * 4);
+    p.tail_val.alloc(tp * vs);
+    if (tp > total) {
+        SPMV_HIP(hipMemsetAsync(p.tail_row.as<int32_t>() + total, 0, (tp - total) * 4, s));
+        SPMV_HIP(hipMemsetAsync(p.tail_col.as<int32_t>() + total, 0, (tp - total) * 4, s));
+        SPMV_HIP(hipMemsetAsync((char *)p.tail_val.p + total * vs, 0, (tp - total) * vs, s));
+    }
     p.partials.alloc(coo_partials_bytes(total, h->dt));
     if (total > 0) {
         const int grid = (int)std::min<int64_t>(ceil_div(h->nnz, kBlock), 65536);

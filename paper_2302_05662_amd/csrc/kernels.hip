@@ -160,6 +160,52 @@ __global__ __launch_bounds__(BLOCK) void csr_vector_kernel(
     if (lane == 0 && row < n_rows) store_y(y, row, acc, alpha, beta);
 }
 
+// ---- CSR vector, 16-byte loads: L lanes per row, 4 consecutive entries per lane ----
+//
+// A lane reads entries [j, j + 4) with one aligned 16-byte load of col and one of
+// val (two for FP64), starting from the row's first entry rounded down to a
+// multiple of 4; entries outside the row are masked before x is touched. The
+// arrays are padded to a multiple of 16 entries, so the last load stays inside.
+
+template <class V, int BLOCK, int L, int UNROLL>
+__global__ __launch_bounds__(BLOCK) void csr_vector4_kernel(
+    int32_t n_rows, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+    const V *__restrict__ val, const V *__restrict__ x, V alpha, V beta, V *__restrict__ y) {
+    constexpr int RPB = BLOCK / L;
+    constexpr int STEP = 4 * L;  // entries a group covers per load
+    __shared__ int32_t s_rp[RPB + 1];
+    const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int64_t row0 = (int64_t)b * RPB;
+    for (int t = threadIdx.x; t <= RPB; t += BLOCK)
+        s_rp[t] = rp[std::min<int64_t>(row0 + t, n_rows)];
+    __syncthreads();
+    const int g = threadIdx.x / L, lane = threadIdx.x % L;
+    const int32_t s = s_rp[g], e = s_rp[g + 1];
+    double acc = 0.0;
+    for (int32_t j = (s & ~3) + 4 * lane; j < e; j += STEP * UNROLL) {
+        Pack<int32_t, 4> c[UNROLL];
+        Pack<V, 4> v[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            if (j + u * STEP < e) {
+                c[u] = ld_i32<4>(col + j + u * STEP);
+                v[u] = ld_val<4>(val + j + u * STEP);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int32_t k = j + u * STEP + q;
+                if (k >= s && k < e) acc += (double)v[u].v[q] * (double)x[c[u].v[q]];
+            }
+        }
+    }
+    acc = group_sum<L>(acc);
+    const int64_t row = row0 + g;
+    if (lane == 0 && row < n_rows) store_y(y, row, acc, alpha, beta);
+}
+
 // ---- ELL: RPT consecutive rows per thread, column-major slots ----------------------
 
 template <class V, int BLOCK, int RPT, int UNROLL>
@@ -464,6 +510,17 @@ void csr_vector_launch(const Args &a) {
     SPMV_CHECK_LAUNCH();
 }
 
+template <class V, int L, int UNROLL>
+void csr_vector4_launch(const Args &a) {
+    const spmv_matrix_s *h = a.h;
+    if (h->n_rows == 0) return;
+    constexpr int BLOCK = 256;
+    csr_vector4_kernel<V, BLOCK, L, UNROLL><<<grid_of(h->n_rows, BLOCK / L), BLOCK, 0, a.s>>>(
+        h->n_rows, h->row_ptr.as<int32_t>(), h->col.as<int32_t>(), h->val.as<V>(),
+        (const V *)a.x, (V)a.alpha, (V)a.beta, (V *)a.y);
+    SPMV_CHECK_LAUNCH();
+}
+
 template <class V, int ITEMS>
 void coo_launch(const Args &a) {
     const spmv_matrix_s *h = a.h;
@@ -500,7 +557,11 @@ void hyb_launch(const Args &a) {
 }
 
 #define V2(kind, blk, lanes, unr, fn) \
-    Variant{{kind, blk, lanes, unr}, fn<float>, fn<double>}
+    Variant{{kind, blk, lanes, unr, 1}, fn<float>, fn<double>}
+#define V4(kind, blk, lanes, unr, fn) \
+    Variant{{kind, blk, lanes, unr, 4}, fn<float>, fn<double>}
+#define VN(kind, blk, lanes, unr, vec, fn) \
+    Variant{{kind, blk, lanes, unr, vec}, fn<float>, fn<double>}
 
 template <class V> void csr_s1(const Args &a) { csr_scalar_launch<V, 1>(a); }
 template <class V> void csr_s4(const Args &a) { csr_scalar_launch<V, 4>(a); }
@@ -513,6 +574,15 @@ CSRV(16, 1) CSRV(16, 2) CSRV(16, 4)
 CSRV(32, 1) CSRV(32, 2) CSRV(32, 4)
 CSRV(64, 1) CSRV(64, 2) CSRV(64, 4)
 #undef CSRV
+#define CSRV4(L, U) \
+    template <class V> void csr_w##L##_##U(const Args &a) { csr_vector4_launch<V, L, U>(a); }
+CSRV4(2, 1) CSRV4(2, 2)
+CSRV4(4, 1) CSRV4(4, 2)
+CSRV4(8, 1) CSRV4(8, 2)
+CSRV4(16, 1) CSRV4(16, 2)
+CSRV4(32, 1) CSRV4(32, 2)
+CSRV4(64, 1) CSRV4(64, 2)
+#undef CSRV4
 template <class V> void coo_2(const Args &a) { coo_launch<V, 2>(a); }
 template <class V> void coo_4(const Args &a) { coo_launch<V, 4>(a); }
 template <class V> void coo_8(const Args &a) { coo_launch<V, 8>(a); }
@@ -549,20 +619,32 @@ const std::vector<Variant> &table(spmv_format f) {
         V2(SPMV_KERNEL_CSR_VECTOR, 256, 64, 1, csr_v64_1),
         V2(SPMV_KERNEL_CSR_VECTOR, 256, 64, 2, csr_v64_2),
         V2(SPMV_KERNEL_CSR_VECTOR, 256, 64, 4, csr_v64_4),
+        V4(SPMV_KERNEL_CSR_VECTOR, 256, 2, 1, csr_w2_1),
+        V4(SPMV_KERNEL_CSR_VECTOR, 256, 2, 2, csr_w2_2),
+        V4(SPMV_KERNEL_CSR_VECTOR, 256, 4, 1, csr_w4_1),
+        V4(SPMV_KERNEL_CSR_VECTOR, 256, 4, 2, csr_w4_2),
+        V4(SPMV_KERNEL_CSR_VECTOR, 256, 8, 1, csr_w8_1),
+        V4(SPMV_KERNEL_CSR_VECTOR, 256, 8, 2, csr_w8_2),
+        V4(SPMV_KERNEL_CSR_VECTOR, 256, 16, 1, csr_w16_1),
+        V4(SPMV_KERNEL_CSR_VECTOR, 256, 16, 2, csr_w16_2),
+        V4(SPMV_KERNEL_CSR_VECTOR, 256, 32, 1, csr_w32_1),
+        V4(SPMV_KERNEL_CSR_VECTOR, 256, 32, 2, csr_w32_2),
+        V4(SPMV_KERNEL_CSR_VECTOR, 256, 64, 1, csr_w64_1),
+        V4(SPMV_KERNEL_CSR_VECTOR, 256, 64, 2, csr_w64_2),
     };
     static const std::vector<Variant> coo = {
-        V2(SPMV_KERNEL_COO, 256, 2, 1, coo_2),
-        V2(SPMV_KERNEL_COO, 256, 4, 1, coo_4),
-        V2(SPMV_KERNEL_COO, 256, 8, 1, coo_8),
+        VN(SPMV_KERNEL_COO, 256, 2, 1, 2, coo_2),
+        VN(SPMV_KERNEL_COO, 256, 4, 1, 4, coo_4),
+        VN(SPMV_KERNEL_COO, 256, 8, 1, 4, coo_8),
     };
     static const std::vector<Variant> ell = {
-        V2(SPMV_KERNEL_ELL, 256, 1, 1, ell_1_1), V2(SPMV_KERNEL_ELL, 256, 1, 2, ell_1_2),
-        V2(SPMV_KERNEL_ELL, 256, 2, 1, ell_2_1), V2(SPMV_KERNEL_ELL, 256, 2, 2, ell_2_2),
-        V2(SPMV_KERNEL_ELL, 256, 4, 1, ell_4_1), V2(SPMV_KERNEL_ELL, 256, 4, 2, ell_4_2),
+        VN(SPMV_KERNEL_ELL, 256, 1, 1, 1, ell_1_1), VN(SPMV_KERNEL_ELL, 256, 1, 2, 1, ell_1_2),
+        VN(SPMV_KERNEL_ELL, 256, 2, 1, 2, ell_2_1), VN(SPMV_KERNEL_ELL, 256, 2, 2, 2, ell_2_2),
+        VN(SPMV_KERNEL_ELL, 256, 4, 1, 4, ell_4_1), VN(SPMV_KERNEL_ELL, 256, 4, 2, 4, ell_4_2),
     };
     static const std::vector<Variant> hyb = {
-        V2(SPMV_KERNEL_HYB, 256, 1, 4, hyb_1_4), V2(SPMV_KERNEL_HYB, 256, 1, 8, hyb_1_8),
-        V2(SPMV_KERNEL_HYB, 256, 2, 4, hyb_2_4), V2(SPMV_KERNEL_HYB, 256, 2, 8, hyb_2_8),
+        VN(SPMV_KERNEL_HYB, 256, 1, 4, 1, hyb_1_4), VN(SPMV_KERNEL_HYB, 256, 1, 8, 1, hyb_1_8),
+        VN(SPMV_KERNEL_HYB, 256, 2, 4, 2, hyb_2_4), VN(SPMV_KERNEL_HYB, 256, 2, 8, 2, hyb_2_8),
     };
     static const std::vector<Variant> none;
     switch (f) {
