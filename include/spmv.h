@@ -209,6 +209,67 @@ spmv_status spmv_features(spmv_handle h, float *out12, void *stream);
 spmv_status spmv_select_format(spmv_handle h, spmv_select_mode m, spmv_format *out,
                                float *out_scores, void *stream);
 
+/* ---- the learned selector (paper, Method: predicting optimal configuration
+ * parameters -- a classifier over the sparsity features; Setup, learning
+ * algorithms: MLP with ReLU, Adam, learning rate 0.001, 200 epochs) -----------
+ *
+ * Network 12-64-64-4 with ReLU; classes are spmv_format values. A model is
+ * 5276 floats: W1[64][12] b1[64] W2[64][64] b2[64] W3[4][64] b3[4] (5252
+ * parameters, each W row-major [out][in]) then the input standardisation
+ * mean[12], std[12]. Inputs are the 12 features of spmv_features with
+ * log2(1 + v) applied to features 0-6, 8 and 9, then (v - mean) / std. */
+
+#define SPMV_SELECTOR_PARAMS 5252
+#define SPMV_SELECTOR_MODEL 5276
+
+typedef struct spmv_train_opts {
+    int32_t epochs;    /* passes over the data (200)                              */
+    int32_t batch;     /* minibatch size; min(batch, n) is used (200)             */
+    int32_t max_steps; /* stop after this many updates; <= 0 means no limit       */
+    float lr;          /* Adam step size (1e-3)                                   */
+    float l2;          /* L2 weight alpha; the loss adds alpha/(2B)*|W|^2 (1e-4)   */
+    float beta1, beta2, eps; /* Adam (0.9, 0.999, 1e-8)                           */
+} spmv_train_opts;
+
+/* Train the selector on the device: mean softmax cross-entropy + L2, minibatch
+ * Adam (Kingma and Ba, Algorithm 1) in the sample order perms gives for each
+ * epoch; the standardisation statistics are the training set's mean and
+ * population std (floored at 1e-6). One workgroup runs every step in one
+ * launch (deterministic).
+ *   feats: device float[n][12] raw features; labels: device int32[n] in 0..3;
+ *   init_params: device float[5252]; perms: device int32[epochs][n], each row a
+ *   permutation of 0..n-1; out_model: device float[5276];
+ *   out_losses: device float[number of steps] or NULL (loss of each step).
+ * Errors: INVALID_ARG, OOM, HIP. Synchronises `stream`. */
+spmv_status spmv_selector_train(const float *feats, const int32_t *labels, int32_t n,
+                                const float *init_params, const int32_t *perms,
+                                const spmv_train_opts *opts, float *out_model, float *out_losses,
+                                void *stream);
+
+/* Loss and gradient of one minibatch (the quantities a training step uses):
+ *   params: device float[5252]; z: device float[b][12] already standardised;
+ *   labels: device int32[b]; loss: device float[1]; grad: device float[5252].
+ * Asynchronous on `stream`. Errors: INVALID_ARG, HIP. */
+spmv_status spmv_selector_loss_grad(const float *params, const float *z, const int32_t *labels,
+                                    int32_t b, float l2, float *loss, float *grad, void *stream);
+
+/* Logits and chosen class for n feature vectors.
+ *   model: device float[5276], or NULL for the weights set on this device;
+ *   feats: device float[n][12] raw features; applicable: device uint8[n][4]
+ *   (nonzero = format allowed) or NULL for all; logits: device float[n][4] or
+ *   NULL; cls: device int32[n] or NULL (arg-max over allowed classes, ties to
+ *   the lowest). Asynchronous. Errors: INVALID_ARG, NO_MODEL, HIP. */
+spmv_status spmv_selector_predict(const float *model, const float *feats, int32_t n,
+                                  const uint8_t *applicable, float *logits, int32_t *cls,
+                                  void *stream);
+
+/* Install / read the weights MODEL selection uses on the current device.
+ *   params: host float[5276]; n must be 5276. set_weights(NULL, 0) forgets the
+ *   model (MODEL selection then returns NO_MODEL).
+ * Errors: INVALID_ARG, NO_MODEL (get before set), HIP. Synchronous. */
+spmv_status spmv_selector_set_weights(const float *params, int64_t n);
+spmv_status spmv_selector_get_weights(float *params, int64_t n);
+
 /* ---- diagnostics ------------------------------------------------------------ */
 
 const char *spmv_status_string(spmv_status s);

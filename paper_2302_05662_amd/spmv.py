@@ -90,6 +90,21 @@ _sig("spmv_tune", _I32, _P, _I32, _P, _P, _I32, ctypes.c_int, ctypes.POINTER(_I3
      ctypes.POINTER(_F), _P)
 _sig("spmv_features", _I32, _P, _P, _P)
 _sig("spmv_select_format", _I32, _P, _I32, ctypes.POINTER(_I32), _P, _P)
+
+
+class spmv_train_opts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("max_steps", ctypes.c_int32), ("lr", ctypes.c_float), ("l2", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
+SPMV_SELECTOR_PARAMS = 5252
+SPMV_SELECTOR_MODEL = 5276
+_sig("spmv_selector_train", _I32, _P, _P, _I32, _P, _P, ctypes.POINTER(spmv_train_opts), _P, _P, _P)
+_sig("spmv_selector_loss_grad", _I32, _P, _P, _P, _I32, _F, _P, _P, _P)
+_sig("spmv_selector_predict", _I32, _P, _P, _I32, _P, _P, _P, _P)
+_sig("spmv_selector_set_weights", _I32, _P, _I64)
+_sig("spmv_selector_get_weights", _I32, _P, _I64)
 _sig("spmv_status_string", ctypes.c_char_p, _I32)
 _sig("spmv_last_error", ctypes.c_char_p)
 
@@ -267,6 +282,77 @@ def spmv_select_format(h: Handle, mode: int, stream=None):
                                    ctypes.c_void_p(scores.ctypes.data), _stream_ptr(stream)),
            "spmv_select_format")
     return int(f.value), scores
+
+
+def _dev_ptr(t, name, allow_none=False):
+    if t is None:
+        if allow_none:
+            return ctypes.c_void_p(0)
+        raise ValueError(f"{name} is required")
+    p, on_dev, _ = _buffer(t)
+    if not on_dev:
+        raise ValueError(f"{name} must be a device tensor")
+    return p
+
+
+def spmv_selector_train(feats, labels, init_params, perms, epochs=200, batch=200, lr=1e-3,
+                        l2=1e-4, beta1=0.9, beta2=0.999, eps=1e-8, max_steps=0, out_model=None,
+                        out_losses=None, stream=None):
+    """Train on the device; returns the model tensor (float32[5276] on the device)."""
+    import torch
+    n = int(feats.shape[0])
+    if out_model is None:
+        out_model = torch.empty(SPMV_SELECTOR_MODEL, dtype=torch.float32, device=feats.device)
+    o = spmv_train_opts(int(epochs), int(batch), int(max_steps), float(lr), float(l2),
+                        float(beta1), float(beta2), float(eps))
+    _check(_lib.spmv_selector_train(_dev_ptr(feats, "feats"), _dev_ptr(labels, "labels"), n,
+                                     _dev_ptr(init_params, "init_params"), _dev_ptr(perms, "perms"),
+                                     ctypes.byref(o), _dev_ptr(out_model, "out_model"),
+                                     _dev_ptr(out_losses, "out_losses", True), _stream_ptr(stream)),
+           "spmv_selector_train")
+    return out_model
+
+
+def spmv_selector_loss_grad(params, z, labels, l2=1e-4, stream=None):
+    """(loss tensor[1], grad tensor[5252]) of one minibatch, on the device."""
+    import torch
+    loss = torch.empty(1, dtype=torch.float32, device=z.device)
+    grad = torch.empty(SPMV_SELECTOR_PARAMS, dtype=torch.float32, device=z.device)
+    _check(_lib.spmv_selector_loss_grad(_dev_ptr(params, "params"), _dev_ptr(z, "z"),
+                                        _dev_ptr(labels, "labels"), int(z.shape[0]), float(l2),
+                                        _dev_ptr(loss, "loss"), _dev_ptr(grad, "grad"),
+                                        _stream_ptr(stream)), "spmv_selector_loss_grad")
+    return loss, grad
+
+
+def spmv_selector_predict(model, feats, applicable=None, stream=None):
+    """(logits[n][4], cls[n]) device tensors; model None = the weights set on this device."""
+    import torch
+    n = int(feats.shape[0])
+    logits = torch.empty((n, 4), dtype=torch.float32, device=feats.device)
+    cls = torch.empty(n, dtype=torch.int32, device=feats.device)
+    _check(_lib.spmv_selector_predict(_dev_ptr(model, "model", True), _dev_ptr(feats, "feats"), n,
+                                      _dev_ptr(applicable, "applicable", True),
+                                      _dev_ptr(logits, "logits"), _dev_ptr(cls, "cls"),
+                                      _stream_ptr(stream)), "spmv_selector_predict")
+    return logits, cls
+
+
+def spmv_selector_set_weights(params):
+    """Install a 5276-float model on the current device; None forgets it."""
+    if params is None:
+        _check(_lib.spmv_selector_set_weights(ctypes.c_void_p(0), 0), "spmv_selector_set_weights")
+        return
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    _check(_lib.spmv_selector_set_weights(ctypes.c_void_p(a.ctypes.data), a.size),
+           "spmv_selector_set_weights")
+
+
+def spmv_selector_get_weights() -> np.ndarray:
+    out = np.zeros(SPMV_SELECTOR_MODEL, dtype=np.float32)
+    _check(_lib.spmv_selector_get_weights(ctypes.c_void_p(out.ctypes.data), out.size),
+           "spmv_selector_get_weights")
+    return out
 
 
 def spmv_status_string(status: int) -> str:
