@@ -353,6 +353,15 @@ __global__ __launch_bounds__(kThreads) void train_kernel(const float *__restrict
     for (int t = threadIdx.x; t < kParams; t += blockDim.x) model[t] = param_of(n, t);
 }
 
+// Every entry of the epoch orders must index a training sample.
+__global__ __launch_bounds__(256) void check_orders(const int32_t *__restrict__ perms, int64_t total,
+                                                    int32_t n, int32_t *__restrict__ bad) {
+    int f = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256)
+        f |= (perms[i] < 0 || perms[i] >= n);
+    if (f) atomicOr(bad, 1);
+}
+
 // One wave per sample: logits, masked arg-max (ties to the lowest class).
 __global__ __launch_bounds__(kThreads) void predict_kernel(const float *__restrict__ model,
                                                            const float *__restrict__ F, int N,
@@ -518,7 +527,17 @@ extern "C" spmv_status spmv_selector_train(const float *feats, const int32_t *la
             fail(SPMV_ERR_INVALID_ARG, "bad argument");
         if (opts->epochs <= 0 || opts->batch <= 0) fail(SPMV_ERR_INVALID_ARG, "bad epochs / batch");
         hipStream_t s = (hipStream_t)stream;
-        DevBuf Z, mv;
+        DevBuf Z, mv, bad;
+        bad.alloc(4);
+        SPMV_HIP(hipMemsetAsync(bad.p, 0, 4, s));
+        const int64_t total = (int64_t)opts->epochs * n;
+        check_orders<<<(int)std::min<int64_t>(ceil_div(total, 256), 2048), 256, 0, s>>>(
+            perms, total, n, bad.as<int32_t>());
+        SPMV_CHECK_LAUNCH();
+        int32_t hb = 0;
+        SPMV_HIP(hipMemcpyAsync(&hb, bad.p, 4, hipMemcpyDeviceToHost, s));
+        SPMV_HIP(hipStreamSynchronize(s));
+        if (hb) fail(SPMV_ERR_INVALID_ARG, "perms holds an index outside [0, %d)", n);
         Z.alloc((int64_t)n * kIn * 4);
         mv.alloc(2 * (int64_t)kParams * 4);
         SPMV_HIP(hipMemcpyAsync(out_model, init_params, kParams * 4, hipMemcpyDeviceToDevice, s));

@@ -149,3 +149,13 @@ def test_exhaustive_and_rule_selection():
     h2 = S.spmv_create(pl.n_rows, pl.n_cols, pl.row, pl.col, pl.values(np.float32))
     fmt2, times2 = S.spmv_select_format(h2, S.SPMV_SELECT_EXHAUSTIVE)
     assert np.isinf(times2[2]) and fmt2 != S.SPMV_FMT_ELL
+
+
+def test_train_rejects_bad_orders():
+    F, labels = _toy(N=20, seed=1)
+    perms = synth.epoch_permutations(1, 20, 2)
+    perms[1, 5] = 20
+    with pytest.raises(S.SpmvError) as e:
+        S.spmv_selector_train(_dev(F), _dev(labels), _dev(synth.glorot_params(1)), _dev(perms),
+                              epochs=2, batch=8)
+    assert e.value.status == "INVALID_ARG"
