@@ -209,6 +209,51 @@ spmv_status spmv_features(spmv_handle h, float *out12, void *stream);
 spmv_status spmv_select_format(spmv_handle h, spmv_select_mode m, spmv_format *out,
                                float *out_scores, void *stream);
 
+/* ---- batched SpMV: many CSR matrices in one persistent launch, captured in a
+ * HIP graph (the stand-in for the paper's compile-time mode, Method:
+ * compile-time optimisation mode, which fixes launch settings per matrix) -- */
+
+typedef struct spmv_batch_config {
+    int32_t block;           /* workgroup size (256)                                 */
+    int32_t unroll;          /* 16-byte loads in flight per lane (1 or 2)            */
+    int32_t passes_per_tile; /* a tile = this many passes of block/lanes rows        */
+    int32_t blocks_per_cu;   /* persistent workgroups per compute unit               */
+    int32_t lanes_divisor;   /* lanes per row = smallest power of two >=
+                                mean row length / (4 * divisor), clamped to 2..64    */
+    int32_t total_tiles;     /* row tiles over the whole batch                       */
+    int32_t grid;            /* workgroups launched                                  */
+    float tuned_ms;          /* median graph time of the chosen setting (0: untuned) */
+} spmv_batch_config;
+
+/* Build a batch over `count` (1..8192) CSR handles of one dtype on the current
+ * device, with y_i = alpha_i * A_i * x_i + beta_i * y_i for each i.
+ *   hs: host array of handles (borrowed: they must outlive the batch);
+ *   xs, ys: host arrays of device pointers (x_i: n_cols_i values, y_i:
+ *   n_rows_i values, not overlapping); alphas, betas: host arrays or NULL (1
+ *   and 0). If tune != 0 every setting of a small grid (unroll, tile size,
+ *   workgroups per CU, lanes rule) is captured and timed and the fastest kept.
+ * Errors: INVALID_ARG, OOM, HIP. Synchronises `stream`. */
+spmv_status spmv_batch_create(spmv_batch *out, const spmv_handle *hs, int32_t count,
+                              const void *const *xs, void *const *ys, const double *alphas,
+                              const double *betas, int tune, void *stream);
+
+/* One graph launch computing every product of the batch. Asynchronous.
+ * Runs on one stream must not overlap (they share the tile counter).
+ * Errors: INVALID_ARG, HIP. */
+spmv_status spmv_batch_run(spmv_batch b, void *stream);
+
+/* Re-point the batch (any array may be NULL to keep it); enqueued on `stream`
+ * before later runs. Errors: INVALID_ARG (the batch is left unchanged), HIP. */
+spmv_status spmv_batch_update(spmv_batch b, const void *const *xs, void *const *ys,
+                              const double *alphas, const double *betas, void *stream);
+
+/* The setting in use, and each matrix's lanes per row (host int32[count] or
+ * NULL). Errors: INVALID_ARG. */
+spmv_status spmv_batch_get_config(spmv_batch b, spmv_batch_config *out, int32_t *lanes);
+
+/* Free the batch (not its handles). NULL is ignored. Synchronises the device. */
+void spmv_batch_destroy(spmv_batch b);
+
 /* ---- the learned selector (paper, Method: predicting optimal configuration
  * parameters -- a classifier over the sparsity features; Setup, learning
  * algorithms: MLP with ReLU, Adam, learning rate 0.001, 200 epochs) -----------

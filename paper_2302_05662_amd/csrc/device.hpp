@@ -1,0 +1,122 @@
+// Device helpers shared by the SpMV kernels and the batched launcher: aligned
+// vector loads of the streamed arrays, the y update and the CSR row body.
+#pragma once
+
+#include "common.hpp"
+
+namespace spmv {
+
+typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// ---- N consecutive elements, loaded with the widest aligned vector ----------------
+
+template <class T, int N> struct Pack { T v[N]; };
+
+template <int N>
+__device__ __forceinline__ Pack<int32_t, N> ld_i32(const int32_t *p) {
+    Pack<int32_t, N> r;
+    if constexpr (N == 1) {
+        r.v[0] = ld_stream(p);
+    } else if constexpr (N == 2) {
+        i32x2 a = __builtin_nontemporal_load((const i32x2 *)p);
+        r.v[0] = a.x; r.v[1] = a.y;
+    } else {
+        static_assert(N % 4 == 0, "");
+#pragma unroll
+        for (int q = 0; q < N; q += 4) {
+            i32x4 a = __builtin_nontemporal_load((const i32x4 *)(p + q));
+            r.v[q] = a.x; r.v[q + 1] = a.y; r.v[q + 2] = a.z; r.v[q + 3] = a.w;
+        }
+    }
+    return r;
+}
+
+template <int N>
+__device__ __forceinline__ Pack<float, N> ld_val(const float *p) {
+    Pack<float, N> r;
+    if constexpr (N == 1) {
+        r.v[0] = ld_stream(p);
+    } else if constexpr (N == 2) {
+        f32x2 a = __builtin_nontemporal_load((const f32x2 *)p);
+        r.v[0] = a.x; r.v[1] = a.y;
+    } else {
+        static_assert(N % 4 == 0, "");
+#pragma unroll
+        for (int q = 0; q < N; q += 4) {
+            f32x4 a = __builtin_nontemporal_load((const f32x4 *)(p + q));
+            r.v[q] = a.x; r.v[q + 1] = a.y; r.v[q + 2] = a.z; r.v[q + 3] = a.w;
+        }
+    }
+    return r;
+}
+
+template <int N>
+__device__ __forceinline__ Pack<double, N> ld_val(const double *p) {
+    Pack<double, N> r;
+    if constexpr (N == 1) {
+        r.v[0] = ld_stream(p);
+    } else {
+        static_assert(N % 2 == 0, "");
+#pragma unroll
+        for (int q = 0; q < N; q += 2) {
+            f64x2 a = __builtin_nontemporal_load((const f64x2 *)(p + q));
+            r.v[q] = a.x; r.v[q + 1] = a.y;
+        }
+    }
+    return r;
+}
+
+// y_i = alpha * s + beta * y_i, with y not read when beta == 0.
+template <class V>
+__device__ __forceinline__ void store_y(V *y, int64_t i, double s, V alpha, V beta) {
+    double r = (double)alpha * s;
+    if (beta != V(0)) r += (double)beta * (double)y[i];
+    y[i] = (V)r;
+}
+
+template <int L>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, L);
+    return v;
+}
+
+// Sum of one CSR row's products by a group of L lanes (L a power of two <= 64).
+// Each lane reads 4 consecutive entries per load with an aligned 16-byte load of
+// col and of val, starting from the row start rounded down to a multiple of 4;
+// entries outside [s, e) are masked before x is read. Arrays are padded to 16
+// entries. Every lane of the group returns the same total.
+template <class V, int L, int UNROLL>
+__device__ __forceinline__ double csr_row_dot4(const int32_t *__restrict__ col,
+                                               const V *__restrict__ val,
+                                               const V *__restrict__ x, int32_t s, int32_t e,
+                                               int lane) {
+    constexpr int STEP = 4 * L;
+    double acc = 0.0;
+    for (int32_t j = (s & ~3) + 4 * lane; j < e; j += STEP * UNROLL) {
+        Pack<int32_t, 4> c[UNROLL];
+        Pack<V, 4> v[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            if (j + u * STEP < e) {
+                c[u] = ld_i32<4>(col + j + u * STEP);
+                v[u] = ld_val<4>(val + j + u * STEP);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int32_t k = j + u * STEP + q;
+                if (k >= s && k < e) acc += (double)v[u].v[q] * (double)x[c[u].v[q]];
+            }
+        }
+    }
+    return group_sum<L>(acc);
+}
+
+}  // namespace spmv

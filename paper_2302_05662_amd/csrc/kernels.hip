@@ -12,81 +12,10 @@
 #include <vector>
 
 #include "common.hpp"
+#include "device.hpp"
 
 namespace spmv {
 namespace {
-
-typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
-typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x2 __attribute__((ext_vector_type(2)));
-
-// ---- N consecutive elements, loaded with the widest aligned vector ----------------
-
-template <class T, int N> struct Pack { T v[N]; };
-
-template <int N>
-__device__ __forceinline__ Pack<int32_t, N> ld_i32(const int32_t *p) {
-    Pack<int32_t, N> r;
-    if constexpr (N == 1) {
-        r.v[0] = ld_stream(p);
-    } else if constexpr (N == 2) {
-        i32x2 a = __builtin_nontemporal_load((const i32x2 *)p);
-        r.v[0] = a.x; r.v[1] = a.y;
-    } else {
-        static_assert(N % 4 == 0, "");
-#pragma unroll
-        for (int q = 0; q < N; q += 4) {
-            i32x4 a = __builtin_nontemporal_load((const i32x4 *)(p + q));
-            r.v[q] = a.x; r.v[q + 1] = a.y; r.v[q + 2] = a.z; r.v[q + 3] = a.w;
-        }
-    }
-    return r;
-}
-
-template <int N>
-__device__ __forceinline__ Pack<float, N> ld_val(const float *p) {
-    Pack<float, N> r;
-    if constexpr (N == 1) {
-        r.v[0] = ld_stream(p);
-    } else if constexpr (N == 2) {
-        f32x2 a = __builtin_nontemporal_load((const f32x2 *)p);
-        r.v[0] = a.x; r.v[1] = a.y;
-    } else {
-        static_assert(N % 4 == 0, "");
-#pragma unroll
-        for (int q = 0; q < N; q += 4) {
-            f32x4 a = __builtin_nontemporal_load((const f32x4 *)(p + q));
-            r.v[q] = a.x; r.v[q + 1] = a.y; r.v[q + 2] = a.z; r.v[q + 3] = a.w;
-        }
-    }
-    return r;
-}
-
-template <int N>
-__device__ __forceinline__ Pack<double, N> ld_val(const double *p) {
-    Pack<double, N> r;
-    if constexpr (N == 1) {
-        r.v[0] = ld_stream(p);
-    } else {
-        static_assert(N % 2 == 0, "");
-#pragma unroll
-        for (int q = 0; q < N; q += 2) {
-            f64x2 a = __builtin_nontemporal_load((const f64x2 *)(p + q));
-            r.v[q] = a.x; r.v[q + 1] = a.y;
-        }
-    }
-    return r;
-}
-
-// y_i = alpha * s + beta * y_i, with y not read when beta == 0.
-template <class V>
-__device__ __forceinline__ void store_y(V *y, int64_t i, double s, V alpha, V beta) {
-    double r = (double)alpha * s;
-    if (beta != V(0)) r += (double)beta * (double)y[i];
-    y[i] = (V)r;
-}
 
 // ---- CSR scalar: one thread per row ----------------------------------------------
 
@@ -118,13 +47,6 @@ __global__ __launch_bounds__(BLOCK) void csr_scalar_kernel(
 }
 
 // ---- CSR vector: L lanes of a wavefront per row ------------------------------------
-
-template <int L>
-__device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-    for (int off = L / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, L);
-    return v;
-}
 
 template <class V, int BLOCK, int L, int UNROLL>
 __global__ __launch_bounds__(BLOCK) void csr_vector_kernel(
@@ -172,7 +94,6 @@ __global__ __launch_bounds__(BLOCK) void csr_vector4_kernel(
     int32_t n_rows, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
     const V *__restrict__ val, const V *__restrict__ x, V alpha, V beta, V *__restrict__ y) {
     constexpr int RPB = BLOCK / L;
-    constexpr int STEP = 4 * L;  // entries a group covers per load
     __shared__ int32_t s_rp[RPB + 1];
     const int b = xcd_logical_block(blockIdx.x, gridDim.x);
     const int64_t row0 = (int64_t)b * RPB;
@@ -180,28 +101,7 @@ __global__ __launch_bounds__(BLOCK) void csr_vector4_kernel(
         s_rp[t] = rp[std::min<int64_t>(row0 + t, n_rows)];
     __syncthreads();
     const int g = threadIdx.x / L, lane = threadIdx.x % L;
-    const int32_t s = s_rp[g], e = s_rp[g + 1];
-    double acc = 0.0;
-    for (int32_t j = (s & ~3) + 4 * lane; j < e; j += STEP * UNROLL) {
-        Pack<int32_t, 4> c[UNROLL];
-        Pack<V, 4> v[UNROLL];
-#pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-            if (j + u * STEP < e) {
-                c[u] = ld_i32<4>(col + j + u * STEP);
-                v[u] = ld_val<4>(val + j + u * STEP);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int32_t k = j + u * STEP + q;
-                if (k >= s && k < e) acc += (double)v[u].v[q] * (double)x[c[u].v[q]];
-            }
-        }
-    }
-    acc = group_sum<L>(acc);
+    const double acc = csr_row_dot4<V, L, UNROLL>(col, val, x, s_rp[g], s_rp[g + 1], lane);
     const int64_t row = row0 + g;
     if (lane == 0 && row < n_rows) store_y(y, row, acc, alpha, beta);
 }

@@ -355,6 +355,86 @@ def spmv_selector_get_weights() -> np.ndarray:
     return out
 
 
+class spmv_batch_config(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("unroll", ctypes.c_int32),
+                ("passes_per_tile", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("lanes_divisor", ctypes.c_int32), ("total_tiles", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("tuned_ms", ctypes.c_float)]
+
+
+_sig("spmv_batch_create", _I32, ctypes.POINTER(_P), _P, _I32, _P, _P, _P, _P, ctypes.c_int, _P)
+_sig("spmv_batch_run", _I32, _P, _P)
+_sig("spmv_batch_update", _I32, _P, _P, _P, _P, _P, _P)
+_sig("spmv_batch_get_config", _I32, _P, ctypes.POINTER(spmv_batch_config), _P)
+_sig("spmv_batch_destroy", None, _P)
+
+
+class Batch:
+    """Owns one spmv_batch (and keeps its handles and vectors alive)."""
+
+    def __init__(self, ptr, handles, xs, ys):
+        self.ptr, self.handles, self.xs, self.ys = ptr, list(handles), list(xs), list(ys)
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            _lib.spmv_batch_destroy(self.ptr)
+            self.ptr = None
+
+
+def _ptr_array(items, name):
+    arr = (ctypes.c_void_p * len(items))()
+    for i, t in enumerate(items):
+        arr[i] = _dev_ptr(t, f"{name}[{i}]").value
+    return arr
+
+
+def spmv_batch_create(handles, xs, ys, alphas=None, betas=None, tune=True, stream=None) -> Batch:
+    n = len(handles)
+    hs = (ctypes.c_void_p * n)(*[h.ptr.value if isinstance(h.ptr, ctypes.c_void_p) else h.ptr
+                                 for h in handles])
+    pa = (ctypes.c_double * n)(*alphas) if alphas is not None else None
+    pb = (ctypes.c_double * n)(*betas) if betas is not None else None
+    out = ctypes.c_void_p()
+    _check(_lib.spmv_batch_create(ctypes.byref(out), ctypes.cast(hs, ctypes.c_void_p), n,
+                                  ctypes.cast(_ptr_array(xs, "xs"), ctypes.c_void_p),
+                                  ctypes.cast(_ptr_array(ys, "ys"), ctypes.c_void_p),
+                                  ctypes.cast(pa, ctypes.c_void_p) if pa is not None else None,
+                                  ctypes.cast(pb, ctypes.c_void_p) if pb is not None else None,
+                                  int(bool(tune)), _stream_ptr(stream)), "spmv_batch_create")
+    return Batch(out, handles, xs, ys)
+
+
+def spmv_batch_run(b: Batch, stream=None):
+    _check(_lib.spmv_batch_run(b.ptr, _stream_ptr(stream)), "spmv_batch_run")
+
+
+def spmv_batch_update(b: Batch, xs=None, ys=None, alphas=None, betas=None, stream=None):
+    n = len(b.handles)
+    px = ctypes.cast(_ptr_array(xs, "xs"), ctypes.c_void_p) if xs is not None else None
+    py = ctypes.cast(_ptr_array(ys, "ys"), ctypes.c_void_p) if ys is not None else None
+    pa = ctypes.cast((ctypes.c_double * n)(*alphas), ctypes.c_void_p) if alphas is not None else None
+    pb = ctypes.cast((ctypes.c_double * n)(*betas), ctypes.c_void_p) if betas is not None else None
+    _check(_lib.spmv_batch_update(b.ptr, px, py, pa, pb, _stream_ptr(stream)), "spmv_batch_update")
+    if xs is not None:
+        b.xs = list(xs)
+    if ys is not None:
+        b.ys = list(ys)
+
+
+def spmv_batch_get_config(b: Batch):
+    c = spmv_batch_config()
+    lanes = np.zeros(len(b.handles), dtype=np.int32)
+    _check(_lib.spmv_batch_get_config(b.ptr, ctypes.byref(c), ctypes.c_void_p(lanes.ctypes.data)),
+           "spmv_batch_get_config")
+    return {f: getattr(c, f) for f, _ in c._fields_}, lanes
+
+
+def spmv_batch_destroy(b: Batch):
+    if b.ptr:
+        _lib.spmv_batch_destroy(b.ptr)
+        b.ptr = None
+
+
 def spmv_status_string(status: int) -> str:
     return _lib.spmv_status_string(int(status)).decode()
 
