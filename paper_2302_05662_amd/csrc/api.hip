@@ -112,13 +112,14 @@ spmv_format select_exhaustive(spmv_matrix_s *h, float scores[4], hipStream_t s) 
     return bf;
 }
 
-// Fixed thresholds on the features (a baseline for the learned selector).
+// Fixed thresholds on the features (a baseline for the learned selector):
+// ELL when it pads little, HYB when a few rows are far longer than the rest
+// and its COO tail stays small, CSR otherwise.
 spmv_format select_rule(const float f[12], float votes[4]) {
-    const double mean = f[2], sd = f[4], ell_ratio = f[7], mx = f[8], tail = f[11];
+    const double mean = f[2], ell_ratio = f[7], mx = f[8], tail = f[11];
     spmv_format r = SPMV_FMT_CSR;
-    if (mean > 0 && sd / mean < 0.1 && ell_ratio >= 0.8) r = SPMV_FMT_ELL;
-    else if (mean > 0 && mx > 16 * mean && tail < 0.5) r = SPMV_FMT_HYB;
-    else if (mean < 4) r = SPMV_FMT_COO;
+    if (ell_ratio >= 0.9) r = SPMV_FMT_ELL;
+    else if (mean > 0 && mx > 32 * mean && tail < 0.3) r = SPMV_FMT_HYB;
     for (int i = 0; i < 4; ++i) votes[i] = (i == (int)r) ? 1.f : 0.f;
     return r;
 }

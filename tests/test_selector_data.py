@@ -1,0 +1,67 @@
+"""The committed selector dataset and model (CPU only).
+
+The dataset holds GPU measurements (features and cold per-format times on one
+MI355X); the model was trained from it by the GPU trainer. Here the oracle
+network re-checks both: the model's own predictions, recomputed in FP64, must
+beat always-CSR on the held-out matrices, and the oracle trained on the same
+data must reach a comparable accuracy.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import mlp as OM
+
+PKG = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2302_05662_amd")
+DATA = os.path.join(PKG, "selector_data_mi355x.npz")
+MODEL = os.path.join(PKG, "selector_model.npy")
+
+
+@pytest.fixture(scope="module")
+def data():
+    d = dict(np.load(DATA, allow_pickle=False))
+    d["label"] = np.argmin(d["t_label"], axis=1)
+    d["train"] = (d["seed"] >= 5000) & (d["seed"] <= 6499)
+    d["held"] = (d["seed"] >= 6500) & (d["seed"] <= 6999)
+    return d
+
+
+def _regret(chosen, t):
+    return t[np.arange(len(chosen)), chosen] / t.min(axis=1) - 1.0
+
+
+def test_dataset_shape_and_seeds(data):
+    assert data["train"].sum() == 1500 and data["held"].sum() == 500
+    assert data["feats"].shape == (2000, 12)
+    assert np.all(np.isfinite(data["t_label"][:, [0, 1, 3]]))  # CSR, COO, HYB always apply
+    specs = synth.config5_specs(data["seed"][:5].tolist())
+    assert [s["family"] for s in specs] == data["family"][:5].tolist()
+    assert np.all(data["feats"][:, 0] == data["n_rows"]) and np.all(data["feats"][:, 1] == data["nnz"].astype(np.float32))
+
+
+def test_committed_model_beats_always_csr(data):
+    model = np.load(MODEL).astype(np.float64)
+    held = data["held"]
+    app = np.isfinite(data["t_check"][held])
+    pred, _ = OM.predict(model[:5252], model[5252:5264], model[5264:5276], data["feats"][held],
+                         applicable=app)
+    r_model = _regret(pred, data["t_check"][held])
+    r_csr = _regret(np.zeros(held.sum(), np.int64), data["t_check"][held])
+    assert r_model.mean() <= 0.05
+    assert r_model.mean() < 0.5 * r_csr.mean()
+    ev = json.load(open(os.path.join(PKG, "selector_eval.json")))
+    assert abs(ev["model"]["mean_regret"] - r_model.mean()) < 0.01
+
+
+def test_oracle_training_on_the_data_reaches_the_same_quality(data):
+    tr, held = data["train"], data["held"]
+    p0 = synth.glorot_params(5)
+    perms = synth.epoch_permutations(5, int(tr.sum()), 60)
+    theta, mean, std, _ = OM.train(p0, data["feats"][tr], data["label"][tr], perms)
+    app = np.isfinite(data["t_check"][held])
+    pred, _ = OM.predict(theta, mean, std, data["feats"][held], applicable=app)
+    assert (pred == data["label"][held]).mean() >= 0.9
+    assert _regret(pred, data["t_check"][held]).mean() <= 0.05
