@@ -69,9 +69,13 @@ def load_traffic(kernel_key):
 
 def kernel_symbols(fmt, info, dtype="float"):
     """Substrings of the HIP kernel names one spmv_run of (fmt, variant) launches, main kernel first."""
-    b, l, u, v = info["block"], info["lanes"], info["unroll"], info["vec"]
+    b, l, u, v, pp = info["block"], info["lanes"], info["unroll"], info["vec"], info["pipelined"]
     if info["kernel"] == "csr_scalar":
         return [f"csr_scalar_kernel<{dtype}, {b}, {u}>"]
+    if info["kernel"] == "csr_vector" and pp:
+        return [f"csr_pipe_kernel<{dtype}, {b}, {l}, {pp}>"]
+    if info["kernel"] == "ell" and pp:
+        return [f"ell_pipe_kernel<{dtype}, {b}, {l}>"]
     if info["kernel"] == "csr_vector":
         name = "csr_vector4_kernel" if v == 4 else "csr_vector_kernel"
         return [f"{name}<{dtype}, {b}, {l}, {u}>"]
@@ -399,7 +403,7 @@ def main():
     for e, (ms, cnt) in zip(mats, per_launch):
         info = S.spmv_variant_describe(e["fmt"], S.SPMV_F32, e["variant"][e["fmt"]])
         key = (f"{info['kernel']}_b{info['block']}_l{info['lanes']}_u{info['unroll']}"
-               f"_v{info['vec']}_f32")
+               f"_v{info['vec']}_p{info['pipelined']}_f32")
         g = groups.setdefault(key, {"ms": 0.0, "launches": 0, "bytes": 0.0,
                                     "symbols": kernel_symbols(e["fmt"], info)})
         g["ms"] += ms

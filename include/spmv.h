@@ -79,6 +79,9 @@ typedef struct spmv_variant_info {
                        COO: entries per thread; CSR scalar: 1                      */
     int32_t unroll; /* independent loads in flight per lane                        */
     int32_t vec;    /* consecutive entries each lane reads with one load (1 or 4)  */
+    int32_t pipelined; /* 0: plain; > 0: software pipelined (the next chunk's loads
+                          in flight during the current gathers); for CSR the number
+                          of rows each lane group walks as one stream             */
 } spmv_variant_info;
 
 /* Borrowed view of a format's device arrays; valid until spmv_destroy or a

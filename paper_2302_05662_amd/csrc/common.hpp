@@ -85,11 +85,12 @@ struct DevBuf {
 
 inline size_t dtype_size(spmv_dtype dt) { return dt == SPMV_F64 ? 8 : 4; }
 
-// Streamed index/value arrays are allocated with room for a multiple of 16
-// entries, so a kernel may issue an aligned 16-byte load that covers the last
-// entry. The padding is zero-filled and never contributes to a result.
+// Streamed index/value arrays are allocated with at least one whole group of
+// 16 entries past the last one (a multiple of 16, never empty), so a kernel may
+// issue an aligned 16-byte load at any 4-aligned position <= nnz. The padding
+// is zero-filled and never contributes to a result.
 constexpr int64_t kArrayPad = 16;
-inline int64_t padded_count(int64_t n) { return (n + kArrayPad - 1) / kArrayPad * kArrayPad; }
+inline int64_t padded_count(int64_t n) { return (n / kArrayPad + 1) * kArrayPad; }
 
 // ---- the matrix handle ----------------------------------------------------------
 

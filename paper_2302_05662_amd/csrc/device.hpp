@@ -119,4 +119,68 @@ __device__ __forceinline__ double csr_row_dot4(const int32_t *__restrict__ col,
     return group_sum<L>(acc);
 }
 
+// Software-pipelined CSR rows: a group of L lanes walks PASSES rows (row g of
+// each pass, bounds in s_rp[p * RPB + g], s_rp[p * RPB + g + 1]) as one stream
+// of 4L-entry chunks. Per chunk it issues the x gathers of the current chunk,
+// then the col/val loads of the next chunk (the next row's first chunk at a row
+// end), and only then accumulates, so HBM latency overlaps gather latency and
+// the row reductions. The loop and every state change are wave-uniform (one
+// loop while any group of the wave is active, selects instead of branches, an
+// empty row counts as one fully masked chunk, the group reduction runs every
+// chunk and only its store is conditional), so lane groups never diverge
+// around the shuffles.
+template <class V, int L, int RPB, int PASSES>
+__device__ __forceinline__ void csr_rows_pipelined(const int32_t *__restrict__ col,
+                                                   const V *__restrict__ val,
+                                                   const V *__restrict__ x,
+                                                   const int32_t *s_rp, int g, int lane,
+                                                   int64_t row0, int32_t n_rows, V *__restrict__ y,
+                                                   V alpha, V beta) {
+    constexpr int STEP = 4 * L;
+    int p = 0, t = 0;
+    int32_t s = s_rp[g], e = s_rp[g + 1];
+    int32_t base = s & ~3;
+    int32_t chunks = e > s ? (e - base + STEP - 1) / STEP : 1;
+    int32_t j = base + 4 * lane;
+    // a load address inside the arrays whatever the row: its own chunk, or its start
+    Pack<int32_t, 4> c = ld_i32<4>(col + (j < e ? j : base));
+    Pack<V, 4> v = ld_val<4>(val + (j < e ? j : base));
+    double acc = 0.0;
+    bool active = true;
+    while (__any(active)) {
+        V xv[4];
+        bool ok[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            ok[q] = active && (j + q >= s) && (j + q < e);
+            xv[q] = x[ok[q] ? c.v[q] : 0];
+        }
+        const bool row_done = active && (t + 1 >= chunks);
+        const int pn = row_done ? p + 1 : p;
+        const bool next_active = active && pn < PASSES;
+        const int q_idx = (pn < PASSES ? pn : p) * RPB + g;
+        const int32_t sr = s_rp[q_idx], er = s_rp[q_idx + 1];
+        const int32_t sn = row_done ? sr : s, en = row_done ? er : e;
+        const int32_t basen = sn & ~3;
+        const int32_t chunksn = row_done ? (en > sn ? (en - basen + STEP - 1) / STEP : 1) : chunks;
+        const int tn = row_done ? 0 : t + 1;
+        const int32_t jn = basen + tn * STEP + 4 * lane;
+        const int32_t jl = (next_active && jn < en) ? jn : (j < e ? j : base);
+        const Pack<int32_t, 4> cn = ld_i32<4>(col + jl);
+        const Pack<V, 4> vn = ld_val<4>(val + jl);
+        // a select, not a branch: keeps every gather ahead of the prefetch
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double prod = (double)v.v[q] * (double)xv[q];
+            acc += ok[q] ? prod : 0.0;
+        }
+        const double tot = group_sum<L>(acc);
+        const int64_t row = row0 + (int64_t)p * RPB + g;
+        if (row_done && lane == 0 && row < n_rows) store_y(y, row, tot, alpha, beta);
+        acc = row_done ? 0.0 : acc;
+        active = next_active;
+        p = pn; t = tn; s = sn; e = en; base = basen; chunks = chunksn; j = jn; c = cn; v = vn;
+    }
+}
+
 }  // namespace spmv

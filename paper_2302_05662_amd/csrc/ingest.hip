@@ -355,6 +355,9 @@ extern "C" spmv_status spmv_create(spmv_handle *out, int32_t n_rows, int32_t n_c
         h->col.alloc(np * 4);
         h->val.alloc(np * vs);
         h->row_ptr.alloc(((int64_t)n_rows + 1) * 4);
+        for (DevBuf *b : {&h->row, &h->col})  // padding past the last entry reads as 0
+            SPMV_HIP(hipMemsetAsync(b->as<int32_t>() + nnz, 0, (np - nnz) * 4, s));
+        SPMV_HIP(hipMemsetAsync((char *)h->val.p + nnz * vs, 0, (np - nnz) * vs, s));
         if (nnz > 0) {
             // Stage the input on the device.
             DevBuf in_row, in_col, in_val, flags;
@@ -367,12 +370,10 @@ extern "C" spmv_status spmv_create(spmv_handle *out, int32_t n_rows, int32_t n_c
             SPMV_HIP(hipMemcpyAsync(in_col.p, col, nnz * 4, kind, s));
             SPMV_HIP(hipMemcpyAsync(in_val.p, val, nnz * vs, kind, s));
             SPMV_HIP(hipMemsetAsync(flags.p, 0, 4, s));
-            if (np > nnz) {  // zero the padding of both the staged and the sorted arrays
-                for (DevBuf *b : {&in_row, &in_col, &h->row, &h->col})
-                    SPMV_HIP(hipMemsetAsync(b->as<int32_t>() + nnz, 0, (np - nnz) * 4, s));
-                for (DevBuf *b : {&in_val, &h->val})
-                    SPMV_HIP(hipMemsetAsync((char *)b->p + nnz * vs, 0, (np - nnz) * vs, s));
-            }
+            // zero the padding of the staged arrays (they may become the handle's)
+            for (DevBuf *b : {&in_row, &in_col})
+                SPMV_HIP(hipMemsetAsync(b->as<int32_t>() + nnz, 0, (np - nnz) * 4, s));
+            SPMV_HIP(hipMemsetAsync((char *)in_val.p + nnz * vs, 0, (np - nnz) * vs, s));
             check_coo<<<grid_for(nnz, kBlock, 8192), kBlock, 0, s>>>(
                 in_row.as<int32_t>(), in_col.as<int32_t>(), nnz, n_rows, n_cols,
                 flags.as<int32_t>());

@@ -106,6 +106,70 @@ __global__ __launch_bounds__(BLOCK) void csr_vector4_kernel(
     if (lane == 0 && row < n_rows) store_y(y, row, acc, alpha, beta);
 }
 
+// ---- CSR vector, software pipelined: each lane group walks PASSES rows -------------
+
+template <class V, int BLOCK, int L, int PASSES>
+__global__ __launch_bounds__(BLOCK) void csr_pipe_kernel(
+    int32_t n_rows, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+    const V *__restrict__ val, const V *__restrict__ x, V alpha, V beta, V *__restrict__ y) {
+    constexpr int RPB = BLOCK / L;
+    constexpr int ROWS = RPB * PASSES;
+    __shared__ int32_t s_rp[ROWS + 1];
+    const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int64_t row0 = (int64_t)b * ROWS;
+    for (int t = threadIdx.x; t <= ROWS; t += BLOCK)
+        s_rp[t] = rp[std::min<int64_t>(row0 + t, n_rows)];
+    __syncthreads();
+    csr_rows_pipelined<V, L, RPB, PASSES>(col, val, x, s_rp, threadIdx.x / L, threadIdx.x % L,
+                                          row0, n_rows, y, alpha, beta);
+}
+
+// ---- ELL, software pipelined: the next slot's loads are in flight during the
+// current slot's x gathers --------------------------------------------------------
+
+template <class V, int BLOCK, int RPT>
+__global__ __launch_bounds__(BLOCK) void ell_pipe_kernel(int32_t n_rows, int32_t K, int32_t pitch,
+                                                         const int32_t *__restrict__ ecol,
+                                                         const V *__restrict__ evals,
+                                                         const V *__restrict__ x, V alpha, V beta,
+                                                         V *__restrict__ y) {
+    const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int64_t i0 = ((int64_t)b * BLOCK + threadIdx.x) * RPT;
+    if (i0 >= n_rows) return;
+    double acc[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) acc[q] = 0.0;
+    if (K > 0) {
+        Pack<int32_t, RPT> c = ld_i32<RPT>(ecol + i0);
+        Pack<V, RPT> v = ld_val<RPT>(evals + i0);
+        for (int32_t k = 0; k < K; ++k) {
+            V xv[RPT];
+            bool ok[RPT];
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                ok[q] = c.v[q] >= 0;
+                xv[q] = x[ok[q] ? c.v[q] : 0];
+            }
+            // unconditional prefetch (the last slot is re-read at the end): no branch
+            // around the loads, so the compiler only waits for the gathers below
+            const int64_t off = (int64_t)(k + 1 < K ? k + 1 : k) * pitch + i0;
+            const Pack<int32_t, RPT> cn = ld_i32<RPT>(ecol + off);
+            const Pack<V, RPT> vn = ld_val<RPT>(evals + off);
+            // a select, not a branch: keeps every gather ahead of the prefetch
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const double prod = (double)v.v[q] * (double)xv[q];
+                acc[q] += ok[q] ? prod : 0.0;
+            }
+            c = cn;
+            v = vn;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+        if (i0 + q < n_rows) store_y(y, i0 + q, acc[q], alpha, beta);
+}
+
 // ---- ELL: RPT consecutive rows per thread, column-major slots ----------------------
 
 template <class V, int BLOCK, int RPT, int UNROLL>
@@ -421,6 +485,32 @@ void csr_vector4_launch(const Args &a) {
     SPMV_CHECK_LAUNCH();
 }
 
+template <class V, int L, int PASSES>
+void csr_pipe_launch(const Args &a) {
+    const spmv_matrix_s *h = a.h;
+    if (h->n_rows == 0) return;
+    if (h->nnz == 0) {  // masked gathers read x[0]; with no entries x may be empty
+        csr_vector4_launch<V, L, 1>(a);
+        return;
+    }
+    constexpr int BLOCK = 256;
+    csr_pipe_kernel<V, BLOCK, L, PASSES><<<grid_of(h->n_rows, BLOCK / L * PASSES), BLOCK, 0, a.s>>>(
+        h->n_rows, h->row_ptr.as<int32_t>(), h->col.as<int32_t>(), h->val.as<V>(),
+        (const V *)a.x, (V)a.alpha, (V)a.beta, (V *)a.y);
+    SPMV_CHECK_LAUNCH();
+}
+
+template <class V, int RPT>
+void ell_pipe_launch(const Args &a) {
+    const spmv_matrix_s *h = a.h;
+    if (h->n_rows == 0) return;
+    constexpr int BLOCK = 256;
+    ell_pipe_kernel<V, BLOCK, RPT><<<grid_of(ceil_div(h->n_rows, RPT), BLOCK), BLOCK, 0, a.s>>>(
+        h->n_rows, h->ell.K, h->ell.pitch, h->ell.col.as<int32_t>(), h->ell.val.as<V>(),
+        (const V *)a.x, (V)a.alpha, (V)a.beta, (V *)a.y);
+    SPMV_CHECK_LAUNCH();
+}
+
 template <class V, int ITEMS>
 void coo_launch(const Args &a) {
     const spmv_matrix_s *h = a.h;
@@ -457,11 +547,13 @@ void hyb_launch(const Args &a) {
 }
 
 #define V2(kind, blk, lanes, unr, fn) \
-    Variant{{kind, blk, lanes, unr, 1}, fn<float>, fn<double>}
+    Variant{{kind, blk, lanes, unr, 1, 0}, fn<float>, fn<double>}
 #define V4(kind, blk, lanes, unr, fn) \
-    Variant{{kind, blk, lanes, unr, 4}, fn<float>, fn<double>}
+    Variant{{kind, blk, lanes, unr, 4, 0}, fn<float>, fn<double>}
 #define VN(kind, blk, lanes, unr, vec, fn) \
-    Variant{{kind, blk, lanes, unr, vec}, fn<float>, fn<double>}
+    Variant{{kind, blk, lanes, unr, vec, 0}, fn<float>, fn<double>}
+#define VP(kind, blk, lanes, vec, pipe, fn) \
+    Variant{{kind, blk, lanes, 1, vec, pipe}, fn<float>, fn<double>}
 
 template <class V> void csr_s1(const Args &a) { csr_scalar_launch<V, 1>(a); }
 template <class V> void csr_s4(const Args &a) { csr_scalar_launch<V, 4>(a); }
@@ -483,6 +575,18 @@ CSRV4(16, 1) CSRV4(16, 2)
 CSRV4(32, 1) CSRV4(32, 2)
 CSRV4(64, 1) CSRV4(64, 2)
 #undef CSRV4
+#define CSRP(L, P) \
+    template <class V> void csr_p##L##_##P(const Args &a) { csr_pipe_launch<V, L, P>(a); }
+CSRP(2, 2) CSRP(2, 4)
+CSRP(4, 2) CSRP(4, 4)
+CSRP(8, 2) CSRP(8, 4)
+CSRP(16, 2) CSRP(16, 4)
+CSRP(32, 2) CSRP(32, 4)
+CSRP(64, 2) CSRP(64, 4)
+#undef CSRP
+template <class V> void ell_p1(const Args &a) { ell_pipe_launch<V, 1>(a); }
+template <class V> void ell_p2(const Args &a) { ell_pipe_launch<V, 2>(a); }
+template <class V> void ell_p4(const Args &a) { ell_pipe_launch<V, 4>(a); }
 template <class V> void coo_2(const Args &a) { coo_launch<V, 2>(a); }
 template <class V> void coo_4(const Args &a) { coo_launch<V, 4>(a); }
 template <class V> void coo_8(const Args &a) { coo_launch<V, 8>(a); }
@@ -531,6 +635,18 @@ const std::vector<Variant> &table(spmv_format f) {
         V4(SPMV_KERNEL_CSR_VECTOR, 256, 32, 2, csr_w32_2),
         V4(SPMV_KERNEL_CSR_VECTOR, 256, 64, 1, csr_w64_1),
         V4(SPMV_KERNEL_CSR_VECTOR, 256, 64, 2, csr_w64_2),
+        VP(SPMV_KERNEL_CSR_VECTOR, 256, 2, 4, 2, csr_p2_2),
+        VP(SPMV_KERNEL_CSR_VECTOR, 256, 2, 4, 4, csr_p2_4),
+        VP(SPMV_KERNEL_CSR_VECTOR, 256, 4, 4, 2, csr_p4_2),
+        VP(SPMV_KERNEL_CSR_VECTOR, 256, 4, 4, 4, csr_p4_4),
+        VP(SPMV_KERNEL_CSR_VECTOR, 256, 8, 4, 2, csr_p8_2),
+        VP(SPMV_KERNEL_CSR_VECTOR, 256, 8, 4, 4, csr_p8_4),
+        VP(SPMV_KERNEL_CSR_VECTOR, 256, 16, 4, 2, csr_p16_2),
+        VP(SPMV_KERNEL_CSR_VECTOR, 256, 16, 4, 4, csr_p16_4),
+        VP(SPMV_KERNEL_CSR_VECTOR, 256, 32, 4, 2, csr_p32_2),
+        VP(SPMV_KERNEL_CSR_VECTOR, 256, 32, 4, 4, csr_p32_4),
+        VP(SPMV_KERNEL_CSR_VECTOR, 256, 64, 4, 2, csr_p64_2),
+        VP(SPMV_KERNEL_CSR_VECTOR, 256, 64, 4, 4, csr_p64_4),
     };
     static const std::vector<Variant> coo = {
         VN(SPMV_KERNEL_COO, 256, 2, 1, 2, coo_2),
@@ -541,6 +657,8 @@ const std::vector<Variant> &table(spmv_format f) {
         VN(SPMV_KERNEL_ELL, 256, 1, 1, 1, ell_1_1), VN(SPMV_KERNEL_ELL, 256, 1, 2, 1, ell_1_2),
         VN(SPMV_KERNEL_ELL, 256, 2, 1, 2, ell_2_1), VN(SPMV_KERNEL_ELL, 256, 2, 2, 2, ell_2_2),
         VN(SPMV_KERNEL_ELL, 256, 4, 1, 4, ell_4_1), VN(SPMV_KERNEL_ELL, 256, 4, 2, 4, ell_4_2),
+        VP(SPMV_KERNEL_ELL, 256, 1, 1, 1, ell_p1), VP(SPMV_KERNEL_ELL, 256, 2, 2, 1, ell_p2),
+        VP(SPMV_KERNEL_ELL, 256, 4, 4, 1, ell_p4),
     };
     static const std::vector<Variant> hyb = {
         VN(SPMV_KERNEL_HYB, 256, 1, 4, 1, hyb_1_4), VN(SPMV_KERNEL_HYB, 256, 1, 8, 1, hyb_1_8),

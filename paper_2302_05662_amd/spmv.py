@@ -51,7 +51,8 @@ class SpmvError(RuntimeError):
 
 class spmv_variant_info(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("lanes", ctypes.c_int32), ("unroll", ctypes.c_int32), ("vec", ctypes.c_int32)]
+                ("lanes", ctypes.c_int32), ("unroll", ctypes.c_int32), ("vec", ctypes.c_int32),
+                ("pipelined", ctypes.c_int32)]
 
 
 class spmv_arrays(ctypes.Structure):
@@ -233,7 +234,7 @@ def spmv_variant_describe(fmt: int, dtype_code: int, idx: int) -> dict:
     _check(_lib.spmv_variant_describe(int(fmt), int(dtype_code), int(idx), ctypes.byref(v)),
            "spmv_variant_describe")
     return {"kernel": KERNEL_NAMES[v.kernel], "block": v.block, "lanes": v.lanes,
-            "unroll": v.unroll, "vec": v.vec}
+            "unroll": v.unroll, "vec": v.vec, "pipelined": v.pipelined}
 
 
 def spmv_set_variant(h: Handle, fmt: int, idx: int):
