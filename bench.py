@@ -74,8 +74,10 @@ def kernel_symbols(fmt, info, dtype="float"):
         return [f"csr_scalar_kernel<{dtype}, {b}, {u}>"]
     if info["kernel"] == "csr_vector" and pp:
         return [f"csr_pipe_kernel<{dtype}, {b}, {l}, {pp}>"]
+    if info["kernel"] == "ell" and info.get("ksplit", 1) > 1:
+        return [f"ell_ksplit_kernel<{dtype}, {info['ksplit']}, {l}>"]
     if info["kernel"] == "ell" and pp:
-        return [f"ell_pipe_kernel<{dtype}, {b}, {l}>"]
+        return [f"ell_pipe_kernel<{dtype}, {b}, {l}, {pp}>"]
     if info["kernel"] == "csr_vector":
         name = "csr_vector4_kernel" if v == 4 else "csr_vector_kernel"
         return [f"{name}<{dtype}, {b}, {l}, {u}>"]
@@ -258,7 +260,7 @@ def batched_section(S, torch, synth, count):
             "graph_of_launches_ms": round(graph_ms, 4),
             "persistent_useful_gbps": round(useful / persistent / 1e6, 1),
             "eager_useful_gbps": round(useful / eager_ms / 1e6, 1),
-            "config": {k: cfg[k] for k in ("unroll", "passes_per_tile", "blocks_per_cu",
+            "config": {k: cfg[k] for k in ("tiling", "unroll", "passes_per_tile", "blocks_per_cu",
                                            "lanes_divisor", "grid", "total_tiles")},
             "timing": "median of 10 warm runs, HIP events on the launch stream"}
 
@@ -403,7 +405,7 @@ def main():
     for e, (ms, cnt) in zip(mats, per_launch):
         info = S.spmv_variant_describe(e["fmt"], S.SPMV_F32, e["variant"][e["fmt"]])
         key = (f"{info['kernel']}_b{info['block']}_l{info['lanes']}_u{info['unroll']}"
-               f"_v{info['vec']}_p{info['pipelined']}_f32")
+               f"_v{info['vec']}_p{info['pipelined']}_k{info['ksplit']}_f32")
         g = groups.setdefault(key, {"ms": 0.0, "launches": 0, "bytes": 0.0,
                                     "symbols": kernel_symbols(e["fmt"], info)})
         g["ms"] += ms

@@ -81,7 +81,10 @@ typedef struct spmv_variant_info {
     int32_t vec;    /* consecutive entries each lane reads with one load (1 or 4)  */
     int32_t pipelined; /* 0: plain; > 0: software pipelined (the next chunk's loads
                           in flight during the current gathers); for CSR the number
-                          of rows each lane group walks as one stream             */
+                          of rows each lane group walks as one stream, for ELL the
+                          number of slots loaded ahead                            */
+    int32_t ksplit;    /* ELL: waves of a workgroup sharing one block of rows, each
+                          taking every ksplit-th slot (1 = one thread per row)     */
 } spmv_variant_info;
 
 /* Borrowed view of a format's device arrays; valid until spmv_destroy or a
@@ -222,7 +225,12 @@ typedef struct spmv_batch_config {
     int32_t passes_per_tile; /* a tile = this many passes of block/lanes rows        */
     int32_t blocks_per_cu;   /* persistent workgroups per compute unit               */
     int32_t lanes_divisor;   /* lanes per row = smallest power of two >=
-                                mean row length / (4 * divisor), clamped to 2..64    */
+                                row length / (4 * divisor), clamped to 2..64         */
+    int32_t tiling;          /* 0: per matrix (lanes from the mean row length; y is
+                                bit-equal to the single CSR vector launch with those
+                                lanes and unroll); 1: per tile (lanes from the tile's
+                                longest row; rows of >= 2048 entries get a tile of
+                                their own reduced by the whole workgroup)            */
     int32_t total_tiles;     /* row tiles over the whole batch                       */
     int32_t grid;            /* workgroups launched                                  */
     float tuned_ms;          /* median graph time of the chosen setting (0: untuned) */
@@ -250,9 +258,15 @@ spmv_status spmv_batch_run(spmv_batch b, void *stream);
 spmv_status spmv_batch_update(spmv_batch b, const void *const *xs, void *const *ys,
                               const double *alphas, const double *betas, void *stream);
 
-/* The setting in use, and each matrix's lanes per row (host int32[count] or
- * NULL). Errors: INVALID_ARG. */
+/* The setting in use, and each matrix's lanes per row under the per-matrix
+ * tiling (host int32[count] or NULL). Errors: INVALID_ARG. */
 spmv_status spmv_batch_get_config(spmv_batch b, spmv_batch_config *out, int32_t *lanes);
+
+/* Rebuild the batch's graph with the setting *cfg (block, total_tiles, grid and
+ * tuned_ms are ignored): unroll 1 or 2, passes_per_tile >= 1, blocks_per_cu
+ * >= 1, lanes_divisor >= 1, tiling 0 or 1. Errors: INVALID_ARG, HIP.
+ * Synchronises `stream`. */
+spmv_status spmv_batch_set_config(spmv_batch b, const spmv_batch_config *cfg, void *stream);
 
 /* Free the batch (not its handles). NULL is ignored. Synchronises the device. */
 void spmv_batch_destroy(spmv_batch b);

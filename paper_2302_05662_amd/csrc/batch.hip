@@ -3,16 +3,22 @@
 //
 // This stands in for the paper's compile-time mode (Method: compile-time
 // optimisation mode picks the thread-block size and related settings per
-// matrix): here a batch of matrices shares one launch whose unroll, tile size,
+// matrix): here a batch of matrices shares one launch whose unroll, tiling,
 // grid size and lanes-per-row rule are picked by an autotuner.
 //
-// Work is split into tiles of consecutive rows of one matrix. A fixed grid of
-// workgroups takes tiles from a device counter (atomicAdd) until the counter
-// passes the last tile, so long and short matrices balance across the CUs and
-// every workgroup reaches the exit. The counter is reset by a one-thread
-// kernel node at the head of the graph. Each row is reduced by the same body
-// as the single-matrix CSR vector kernel (csr_row_dot4), so a matrix's y is
-// bit-equal to its single launch with the same lanes and unroll.
+// Work is a list of tiles, each a range of consecutive rows of one matrix with
+// the number of lanes that reduce each of its rows. A fixed grid of workgroups
+// takes tiles from a device counter (atomicAdd) until the counter passes the
+// last tile, so long and short matrices balance across the CUs and every
+// workgroup reaches the exit. The counter is reset by a one-thread kernel node
+// at the head of the graph.
+//
+// Two tilings: per matrix (every tile of a matrix uses the lanes of its mean
+// row length; rows are then reduced exactly like the single-matrix CSR vector
+// kernel, so y is bit-equal to a single launch with the same lanes and unroll),
+// and per tile (a tile takes the lanes of its longest row, and a row of 2048 or
+// more entries gets a tile of its own reduced by the whole workgroup), which
+// keeps power-law rows from setting the tail.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -25,6 +31,8 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kMaxBatch = 8192;
+constexpr int kBlockRow = 8;          // lanes_log2 value meaning "the whole workgroup"
+constexpr int32_t kLongRow = 2048;    // entries from which a row gets its own tile
 
 struct BatchDesc {
     const int32_t *rp;
@@ -33,10 +41,15 @@ struct BatchDesc {
     const void *x;
     void *y;
     int32_t n_rows;
-    int32_t lanes_log2;    // lanes per row = 1 << lanes_log2 (1..6)
-    int32_t rows_per_tile; // a multiple of 256 >> lanes_log2
-    int32_t tile_begin;    // first tile of this matrix
+    int32_t pad;
     double alpha, beta;
+};
+
+struct BatchTile {
+    int32_t matrix;
+    int32_t row_begin;
+    int32_t row_end;
+    int32_t lanes_log2;  // 1..6: 2..64 lanes per row; kBlockRow: 256 lanes, one row per pass
 };
 
 __global__ void reset_counter(int32_t *counter) { *counter = 0; }
@@ -53,30 +66,46 @@ __device__ __forceinline__ void tile_pass(const BatchDesc &d, const int32_t *s_r
 
 template <class V, int UNROLL>
 __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchDesc *__restrict__ desc,
-                                                       int32_t count, int32_t total_tiles,
+                                                       const BatchTile *__restrict__ tiles,
+                                                       int32_t n_tiles,
                                                        int32_t *__restrict__ counter) {
-    extern __shared__ int32_t s_begin[];        // tile_begin of every matrix
-    __shared__ int32_t s_rp[kBlock / 2 + 1];    // row pointers of one pass (>= 2 lanes per row)
+    __shared__ int32_t s_rp[kBlock / 2 + 1];  // row pointers of one pass (>= 2 lanes per row)
     __shared__ int32_t s_tile;
-    for (int i = threadIdx.x; i < count; i += kBlock) s_begin[i] = desc[i].tile_begin;
+    __shared__ double s_part[kBlock / kWave];
     for (;;) {
         if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
         __syncthreads();
         const int32_t t = s_tile;
-        if (t >= total_tiles) break;
-        int lo = 0, hi = count - 1;  // last matrix whose first tile is <= t
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_begin[mid] <= t) lo = mid; else hi = mid - 1;
+        __syncthreads();  // every thread has read s_tile before thread 0 takes the next tile
+        if (t >= n_tiles) break;
+        const BatchTile tl = tiles[t];
+        const BatchDesc d = desc[tl.matrix];
+        if (tl.lanes_log2 == kBlockRow) {
+            // one long row per pass, all 256 lanes: wave shuffles, then LDS across waves
+            for (int64_t r = tl.row_begin; r < tl.row_end; ++r) {
+                const int32_t s = d.rp[r], e = d.rp[r + 1];
+                double p = csr_row_partial4<V, kBlock, UNROLL>(d.col, (const V *)d.val,
+                                                               (const V *)d.x, s, e, threadIdx.x);
+                p = group_sum<kWave>(p);
+                if ((threadIdx.x & (kWave - 1)) == 0) s_part[threadIdx.x / kWave] = p;
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    double tot = 0.0;
+#pragma unroll
+                    for (int w = 0; w < kBlock / kWave; ++w) tot += s_part[w];
+                    store_y((V *)d.y, r, tot, (V)d.alpha, (V)d.beta);
+                }
+                __syncthreads();
+            }
+            continue;
         }
-        const BatchDesc d = desc[lo];
-        const int rpb = kBlock >> d.lanes_log2;  // rows per pass
-        const int64_t row0 = (int64_t)(t - d.tile_begin) * d.rows_per_tile;
-        const int64_t row_end = std::min<int64_t>(row0 + d.rows_per_tile, d.n_rows);
-        for (int64_t r = row0; r < row_end; r += rpb) {
-            for (int i = threadIdx.x; i <= rpb; i += kBlock) s_rp[i] = d.rp[std::min<int64_t>(r + i, row_end)];
+        const int rpb = kBlock >> tl.lanes_log2;  // rows per pass
+        const int64_t row_end = tl.row_end;
+        for (int64_t r = tl.row_begin; r < row_end; r += rpb) {
+            for (int i = threadIdx.x; i <= rpb; i += kBlock)
+                s_rp[i] = d.rp[std::min<int64_t>(r + i, row_end)];
             __syncthreads();
-            switch (d.lanes_log2) {
+            switch (tl.lanes_log2) {
                 case 1: tile_pass<V, 2, UNROLL>(d, s_rp, r, row_end); break;
                 case 2: tile_pass<V, 4, UNROLL>(d, s_rp, r, row_end); break;
                 case 3: tile_pass<V, 8, UNROLL>(d, s_rp, r, row_end); break;
@@ -89,17 +118,16 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchDesc *__restri
     }
 }
 
-using BatchKernel = void (*)(const BatchDesc *, int32_t, int32_t, int32_t *);
+using BatchKernel = void (*)(const BatchDesc *, const BatchTile *, int32_t, int32_t *);
 
 BatchKernel kernel_for(spmv_dtype dt, int unroll) {
     if (dt == SPMV_F64) return unroll == 2 ? batch_kernel<double, 2> : batch_kernel<double, 1>;
     return unroll == 2 ? batch_kernel<float, 2> : batch_kernel<float, 1>;
 }
 
-int lanes_log2_for(const spmv_matrix_s *h, int divisor) {
-    // lanes x 4 entries per load ~ mean row length / divisor, within 2..64 lanes
-    const double mean = h->n_rows ? (double)h->nnz / h->n_rows : 0.0;
-    const double want = mean / (4.0 * divisor);
+// Smallest lanes_log2 in 1..6 whose lanes x 4 entries per load reach len / divisor.
+int lanes_log2_for_len(double len, int divisor) {
+    const double want = len / (4.0 * divisor);
     int lg = 1;
     while (lg < 6 && (double)(1 << lg) < want) ++lg;
     return lg;
@@ -112,8 +140,10 @@ struct spmv_batch_s {
     int device = 0;
     spmv_dtype dt = SPMV_F32;
     std::vector<spmv_matrix_s *> hs;
+    std::vector<std::vector<int32_t>> row_ptr;  // host copies, for tiling
     std::vector<spmv::BatchDesc> desc;
-    spmv::DevBuf d_desc, d_counter;
+    std::vector<int32_t> lanes;  // per matrix, for the per-matrix tiling
+    spmv::DevBuf d_desc, d_tiles, d_counter;
     spmv_batch_config cfg{};
     int num_cu = 0;
     hipStream_t capture_stream = nullptr;
@@ -130,19 +160,40 @@ struct spmv_batch_s {
 namespace spmv {
 namespace {
 
-// Fill the per-matrix tiling for a configuration; returns the total tile count.
-int32_t plan_tiles(spmv_batch_s *b, const spmv_batch_config &c) {
-    int64_t total = 0;
-    for (size_t i = 0; i < b->hs.size(); ++i) {
-        const spmv_matrix_s *h = b->hs[i];
-        BatchDesc &d = b->desc[i];
-        d.lanes_log2 = lanes_log2_for(h, c.lanes_divisor);
-        d.rows_per_tile = (kBlock >> d.lanes_log2) * c.passes_per_tile;
-        d.tile_begin = (int32_t)total;
-        total += ceil_div(h->n_rows, d.rows_per_tile);
-        if (total > INT32_MAX / 2) fail(SPMV_ERR_INVALID_ARG, "batch has too many tiles");
+std::vector<BatchTile> plan_tiles(spmv_batch_s *b, const spmv_batch_config &c) {
+    std::vector<BatchTile> tiles;
+    b->lanes.assign(b->hs.size(), 0);
+    for (size_t m = 0; m < b->hs.size(); ++m) {
+        const spmv_matrix_s *h = b->hs[m];
+        const std::vector<int32_t> &rp = b->row_ptr[m];
+        const int32_t n = h->n_rows;
+        const int lg_mean = lanes_log2_for_len(n ? (double)h->nnz / n : 0.0, c.lanes_divisor);
+        b->lanes[m] = 1 << lg_mean;
+        const int32_t rows_per_tile = (kBlock >> lg_mean) * c.passes_per_tile;
+        if (c.tiling == 0) {
+            for (int32_t r = 0; r < n; r += rows_per_tile)
+                tiles.push_back({(int32_t)m, r, std::min(n, r + rows_per_tile), lg_mean});
+            continue;
+        }
+        int32_t r = 0;
+        while (r < n) {
+            if (rp[r + 1] - rp[r] >= kLongRow) {
+                tiles.push_back({(int32_t)m, r, r + 1, kBlockRow});
+                ++r;
+                continue;
+            }
+            int32_t r_end = r, mx = 0;
+            while (r_end < n && r_end - r < rows_per_tile && rp[r_end + 1] - rp[r_end] < kLongRow) {
+                mx = std::max(mx, rp[r_end + 1] - rp[r_end]);
+                ++r_end;
+            }
+            tiles.push_back({(int32_t)m, r, r_end,
+                             std::max(lg_mean, lanes_log2_for_len(mx, c.lanes_divisor))});
+            r = r_end;
+        }
     }
-    return (int32_t)total;
+    if (tiles.size() > (size_t)INT32_MAX / 2) fail(SPMV_ERR_INVALID_ARG, "batch has too many tiles");
+    return tiles;
 }
 
 void upload_desc(spmv_batch_s *b, hipStream_t s) {
@@ -153,9 +204,15 @@ void upload_desc(spmv_batch_s *b, hipStream_t s) {
 // (Re)build the graph {reset counter, persistent kernel} for configuration c.
 void build_graph(spmv_batch_s *b, const spmv_batch_config &c, hipStream_t user) {
     spmv_batch_config cc = c;
-    cc.total_tiles = plan_tiles(b, cc);
+    const std::vector<BatchTile> tiles = plan_tiles(b, cc);
+    cc.total_tiles = (int32_t)tiles.size();
     cc.grid = std::max(1, std::min(cc.total_tiles, b->num_cu * cc.blocks_per_cu));
     cc.block = kBlock;
+    SPMV_HIP(hipStreamSynchronize(user));  // no earlier run may still read the old tiles
+    b->d_tiles.alloc(std::max<size_t>(tiles.size(), 1) * sizeof(BatchTile));
+    if (!tiles.empty())
+        SPMV_HIP(hipMemcpy(b->d_tiles.p, tiles.data(), tiles.size() * sizeof(BatchTile),
+                           hipMemcpyHostToDevice));
     upload_desc(b, user);
     SPMV_HIP(hipStreamSynchronize(user));
     if (b->exec) { SPMV_HIP(hipGraphExecDestroy(b->exec)); b->exec = nullptr; }
@@ -165,9 +222,8 @@ void build_graph(spmv_batch_s *b, const spmv_batch_config &c, hipStream_t user) 
     reset_counter<<<1, 1, 0, cs>>>(b->d_counter.as<int32_t>());
     if (cc.total_tiles > 0) {
         BatchKernel k = kernel_for(b->dt, cc.unroll);
-        const size_t lds = b->hs.size() * sizeof(int32_t);
-        k<<<cc.grid, kBlock, lds, cs>>>(b->d_desc.as<BatchDesc>(), (int32_t)b->hs.size(),
-                                        cc.total_tiles, b->d_counter.as<int32_t>());
+        k<<<cc.grid, kBlock, 0, cs>>>(b->d_desc.as<BatchDesc>(), b->d_tiles.as<BatchTile>(),
+                                      cc.total_tiles, b->d_counter.as<int32_t>());
     }
     hipError_t launch_err = hipGetLastError();
     hipGraph_t g = nullptr;
@@ -250,6 +306,7 @@ extern "C" spmv_status spmv_batch_create(spmv_batch *out, const spmv_handle *hs,
         b->dt = hs[0] ? hs[0]->dt : SPMV_F32;
         b->hs.assign(hs, hs + count);
         b->desc.resize(count);
+        b->row_ptr.resize(count);
         for (int32_t i = 0; i < count; ++i) {
             spmv_matrix_s *h = hs[i];
             if (!h) fail(SPMV_ERR_INVALID_ARG, "handle %d is NULL", i);
@@ -262,6 +319,9 @@ extern "C" spmv_status spmv_batch_create(spmv_batch *out, const spmv_handle *hs,
             d.n_rows = h->n_rows;
             d.alpha = 1.0;
             d.beta = 0.0;
+            b->row_ptr[i].resize((size_t)h->n_rows + 1);
+            SPMV_HIP(hipMemcpy(b->row_ptr[i].data(), h->row_ptr.p, ((size_t)h->n_rows + 1) * 4,
+                               hipMemcpyDeviceToHost));
         }
         set_io(b, xs, ys, alphas, betas);
         b->d_desc.alloc(count * sizeof(BatchDesc));
@@ -272,6 +332,7 @@ extern "C" spmv_status spmv_batch_create(spmv_batch *out, const spmv_handle *hs,
         dflt.passes_per_tile = 4;
         dflt.blocks_per_cu = 8;
         dflt.lanes_divisor = 1;
+        dflt.tiling = 1;
         if (!tune) {
             build_graph(b, dflt, s);
             return;
@@ -295,19 +356,21 @@ extern "C" spmv_status spmv_batch_create(spmv_batch *out, const spmv_handle *hs,
         }
         double best = INFINITY;
         spmv_batch_config bc = dflt;
-        for (int unroll : {1, 2})
-            for (int passes : {1, 4, 16})
-                for (int bpc : {4, 8})
-                    for (int div : {1, 2}) {
-                        spmv_batch_config c{};
-                        c.unroll = unroll;
-                        c.passes_per_tile = passes;
-                        c.blocks_per_cu = bpc;
-                        c.lanes_divisor = div;
-                        build_graph(b, c, s);
-                        const double t = time_graph(b, 5, s);
-                        if (t < best) { best = t; bc = b->cfg; }
-                    }
+        for (int tiling : {0, 1})
+            for (int unroll : {1, 2})
+                for (int passes : {1, 4, 16})
+                    for (int bpc : {4, 8})
+                        for (int div : {1, 2}) {
+                            spmv_batch_config c{};
+                            c.tiling = tiling;
+                            c.unroll = unroll;
+                            c.passes_per_tile = passes;
+                            c.blocks_per_cu = bpc;
+                            c.lanes_divisor = div;
+                            build_graph(b, c, s);
+                            const double t = time_graph(b, 5, s);
+                            if (t < best) { best = t; bc = b->cfg; }
+                        }
         SPMV_HIP(hipStreamSynchronize(s));
         for (int32_t i = 0; i < count; ++i) b->desc[i].y = real_y[i];
         build_graph(b, bc, s);
@@ -345,7 +408,18 @@ extern "C" spmv_status spmv_batch_get_config(spmv_batch b, spmv_batch_config *ou
         if (!b || !out) fail(SPMV_ERR_INVALID_ARG, "NULL argument");
         *out = b->cfg;
         if (lanes)
-            for (size_t i = 0; i < b->desc.size(); ++i) lanes[i] = 1 << b->desc[i].lanes_log2;
+            for (size_t i = 0; i < b->lanes.size(); ++i) lanes[i] = b->lanes[i];
+    });
+}
+
+extern "C" spmv_status spmv_batch_set_config(spmv_batch b, const spmv_batch_config *cfg,
+                                             void *stream) {
+    return guard([&] {
+        if (!b || !cfg) fail(SPMV_ERR_INVALID_ARG, "NULL argument");
+        if ((cfg->unroll != 1 && cfg->unroll != 2) || cfg->passes_per_tile < 1 ||
+            cfg->blocks_per_cu < 1 || cfg->lanes_divisor < 1 || (cfg->tiling != 0 && cfg->tiling != 1))
+            fail(SPMV_ERR_INVALID_ARG, "bad batch setting");
+        build_graph(b, *cfg, (hipStream_t)stream);
     });
 }
 

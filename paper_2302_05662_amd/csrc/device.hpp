@@ -85,17 +85,14 @@ __device__ __forceinline__ double group_sum(double v) {
     return v;
 }
 
-// Sum of one CSR row's products by a group of L lanes (L a power of two <= 64).
-// Each lane reads 4 consecutive entries per load with an aligned 16-byte load of
-// col and of val, starting from the row start rounded down to a multiple of 4;
-// entries outside [s, e) are masked before x is read. Arrays are padded to 16
-// entries. Every lane of the group returns the same total.
-template <class V, int L, int UNROLL>
-__device__ __forceinline__ double csr_row_dot4(const int32_t *__restrict__ col,
-                                               const V *__restrict__ val,
-                                               const V *__restrict__ x, int32_t s, int32_t e,
-                                               int lane) {
-    constexpr int STEP = 4 * L;
+// One lane's share of a CSR row's products when NL lanes read 4 consecutive
+// entries each per load (aligned 16-byte loads, masked at the row edges).
+template <class V, int NL, int UNROLL>
+__device__ __forceinline__ double csr_row_partial4(const int32_t *__restrict__ col,
+                                                   const V *__restrict__ val,
+                                                   const V *__restrict__ x, int32_t s, int32_t e,
+                                                   int lane) {
+    constexpr int STEP = 4 * NL;
     double acc = 0.0;
     for (int32_t j = (s & ~3) + 4 * lane; j < e; j += STEP * UNROLL) {
         Pack<int32_t, 4> c[UNROLL];
@@ -116,7 +113,20 @@ __device__ __forceinline__ double csr_row_dot4(const int32_t *__restrict__ col,
             }
         }
     }
-    return group_sum<L>(acc);
+    return acc;
+}
+
+// Sum of one CSR row's products by a group of L lanes (L a power of two <= 64).
+// Each lane reads 4 consecutive entries per load with an aligned 16-byte load of
+// col and of val, starting from the row start rounded down to a multiple of 4;
+// entries outside [s, e) are masked before x is read. Arrays are padded to 16
+// entries. Every lane of the group returns the same total.
+template <class V, int L, int UNROLL>
+__device__ __forceinline__ double csr_row_dot4(const int32_t *__restrict__ col,
+                                               const V *__restrict__ val,
+                                               const V *__restrict__ x, int32_t s, int32_t e,
+                                               int lane) {
+    return group_sum<L>(csr_row_partial4<V, L, UNROLL>(col, val, x, s, e, lane));
 }
 
 // Software-pipelined CSR rows: a group of L lanes walks PASSES rows (row g of
@@ -155,6 +165,7 @@ __device__ __forceinline__ void csr_rows_pipelined(const int32_t *__restrict__ c
             ok[q] = active && (j + q >= s) && (j + q < e);
             xv[q] = x[ok[q] ? c.v[q] : 0];
         }
+        __builtin_amdgcn_sched_barrier(0);  // gathers issue before the prefetch
         const bool row_done = active && (t + 1 >= chunks);
         const int pn = row_done ? p + 1 : p;
         const bool next_active = active && pn < PASSES;
@@ -168,6 +179,7 @@ __device__ __forceinline__ void csr_rows_pipelined(const int32_t *__restrict__ c
         const int32_t jl = (next_active && jn < en) ? jn : (j < e ? j : base);
         const Pack<int32_t, 4> cn = ld_i32<4>(col + jl);
         const Pack<V, 4> vn = ld_val<4>(val + jl);
+        __builtin_amdgcn_sched_barrier(0);  // and the prefetch before the products
         // a select, not a branch: keeps every gather ahead of the prefetch
 #pragma unroll
         for (int q = 0; q < 4; ++q) {

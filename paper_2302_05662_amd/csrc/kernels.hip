@@ -127,7 +127,7 @@ __global__ __launch_bounds__(BLOCK) void csr_pipe_kernel(
 // ---- ELL, software pipelined: the next slot's loads are in flight during the
 // current slot's x gathers --------------------------------------------------------
 
-template <class V, int BLOCK, int RPT>
+template <class V, int BLOCK, int RPT, int DEPTH>
 __global__ __launch_bounds__(BLOCK) void ell_pipe_kernel(int32_t n_rows, int32_t K, int32_t pitch,
                                                          const int32_t *__restrict__ ecol,
                                                          const V *__restrict__ evals,
@@ -139,35 +139,128 @@ __global__ __launch_bounds__(BLOCK) void ell_pipe_kernel(int32_t n_rows, int32_t
     double acc[RPT];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) acc[q] = 0.0;
+    using CI = Pack<int32_t, RPT>;
+    using CV = Pack<V, RPT>;
+    // slot k's gathers, then the load of slot `ahead` into (cn, vn), then slot k's
+    // products (a select, not a branch, so every gather stays ahead of the load).
+    // Buffers rotate by unrolling, never by copying a register a load is still
+    // writing, so the wait before the products covers the gathers only.
+    auto step = [&](const CI &c, const CV &v, int32_t ahead, CI &cn, CV &vn) {
+        V xv[RPT];
+        bool ok[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            ok[q] = c.v[q] >= 0;
+            xv[q] = x[ok[q] ? c.v[q] : 0];
+        }
+        __builtin_amdgcn_sched_barrier(0);  // gathers issue before the prefetch ...
+        const int64_t off = (int64_t)(ahead < K ? ahead : K - 1) * pitch + i0;
+        cn = ld_i32<RPT>(ecol + off);
+        vn = ld_val<RPT>(evals + off);
+        __builtin_amdgcn_sched_barrier(0);  // ... and the prefetch before the products
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const double prod = (double)v.v[q] * (double)xv[q];
+            acc[q] += ok[q] ? prod : 0.0;
+        }
+    };
     if (K > 0) {
-        Pack<int32_t, RPT> c = ld_i32<RPT>(ecol + i0);
-        Pack<V, RPT> v = ld_val<RPT>(evals + i0);
-        for (int32_t k = 0; k < K; ++k) {
-            V xv[RPT];
-            bool ok[RPT];
-#pragma unroll
-            for (int q = 0; q < RPT; ++q) {
-                ok[q] = c.v[q] >= 0;
-                xv[q] = x[ok[q] ? c.v[q] : 0];
+        CI cA = ld_i32<RPT>(ecol + i0), cB, cC;
+        CV vA = ld_val<RPT>(evals + i0), vB, vC;
+        int32_t k = 0;
+        if constexpr (DEPTH == 1) {
+            for (;;) {
+                step(cA, vA, k + 1, cB, vB);
+                if (++k >= K) break;
+                step(cB, vB, k + 1, cA, vA);
+                if (++k >= K) break;
             }
-            // unconditional prefetch (the last slot is re-read at the end): no branch
-            // around the loads, so the compiler only waits for the gathers below
-            const int64_t off = (int64_t)(k + 1 < K ? k + 1 : k) * pitch + i0;
-            const Pack<int32_t, RPT> cn = ld_i32<RPT>(ecol + off);
-            const Pack<V, RPT> vn = ld_val<RPT>(evals + off);
-            // a select, not a branch: keeps every gather ahead of the prefetch
-#pragma unroll
-            for (int q = 0; q < RPT; ++q) {
-                const double prod = (double)v.v[q] * (double)xv[q];
-                acc[q] += ok[q] ? prod : 0.0;
+        } else {
+            const int64_t off1 = (int64_t)(K > 1 ? 1 : 0) * pitch + i0;
+            cB = ld_i32<RPT>(ecol + off1);
+            vB = ld_val<RPT>(evals + off1);
+            for (;;) {
+                step(cA, vA, k + 2, cC, vC);
+                if (++k >= K) break;
+                step(cB, vB, k + 2, cA, vA);
+                if (++k >= K) break;
+                step(cC, vC, k + 2, cB, vB);
+                if (++k >= K) break;
             }
-            c = cn;
-            v = vn;
         }
     }
 #pragma unroll
     for (int q = 0; q < RPT; ++q)
         if (i0 + q < n_rows) store_y(y, i0 + q, acc[q], alpha, beta);
+}
+
+// ---- ELL, slots split across the waves of a workgroup ----------------------------
+//
+// Wave w of the KS waves handles slots w, w + KS, w + 2 KS, ... of the same
+// 64 * RPT rows (one contiguous 256-byte run per slot and wave), with the
+// gather-then-prefetch order of the pipelined kernel; the KS partial sums are
+// added in LDS in wave order. For wide, short matrices this gives KS times the
+// waves of one thread per row.
+
+template <class V, int KS, int RPT>
+__global__ __launch_bounds__(64 * KS) void ell_ksplit_kernel(int32_t n_rows, int32_t K,
+                                                             int32_t pitch,
+                                                             const int32_t *__restrict__ ecol,
+                                                             const V *__restrict__ evals,
+                                                             const V *__restrict__ x, V alpha,
+                                                             V beta, V *__restrict__ y) {
+    __shared__ double s_acc[KS][64 * RPT];
+    const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int64_t i0 = ((int64_t)b * 64 + lane) * RPT;
+    double acc[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) acc[q] = 0.0;
+    using CI = Pack<int32_t, RPT>;
+    using CV = Pack<V, RPT>;
+    const bool live = i0 < n_rows;
+    auto step = [&](const CI &c, const CV &v, int32_t ahead, CI &cn, CV &vn) {
+        V xv[RPT];
+        bool ok[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            ok[q] = c.v[q] >= 0;
+            xv[q] = x[ok[q] ? c.v[q] : 0];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        const int64_t off = (int64_t)(ahead < K ? ahead : w) * pitch + i0;
+        cn = ld_i32<RPT>(ecol + off);
+        vn = ld_val<RPT>(evals + off);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const double prod = (double)v.v[q] * (double)xv[q];
+            acc[q] += ok[q] ? prod : 0.0;
+        }
+    };
+    if (live && w < K) {
+        CI cA = ld_i32<RPT>(ecol + (int64_t)w * pitch + i0), cB;
+        CV vA = ld_val<RPT>(evals + (int64_t)w * pitch + i0), vB;
+        int32_t k = w;
+        for (;;) {
+            step(cA, vA, k + KS, cB, vB);
+            if ((k += KS) >= K) break;
+            step(cB, vB, k + KS, cA, vA);
+            if ((k += KS) >= K) break;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) s_acc[w][lane * RPT + q] = acc[q];
+    __syncthreads();
+    if (w == 0 && live) {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            double t = s_acc[0][lane * RPT + q];
+#pragma unroll
+            for (int p = 1; p < KS; ++p) t += s_acc[p][lane * RPT + q];
+            if (i0 + q < n_rows) store_y(y, i0 + q, t, alpha, beta);
+        }
+    }
 }
 
 // ---- ELL: RPT consecutive rows per thread, column-major slots ----------------------
@@ -500,12 +593,12 @@ void csr_pipe_launch(const Args &a) {
     SPMV_CHECK_LAUNCH();
 }
 
-template <class V, int RPT>
+template <class V, int RPT, int DEPTH>
 void ell_pipe_launch(const Args &a) {
     const spmv_matrix_s *h = a.h;
     if (h->n_rows == 0) return;
     constexpr int BLOCK = 256;
-    ell_pipe_kernel<V, BLOCK, RPT><<<grid_of(ceil_div(h->n_rows, RPT), BLOCK), BLOCK, 0, a.s>>>(
+    ell_pipe_kernel<V, BLOCK, RPT, DEPTH><<<grid_of(ceil_div(h->n_rows, RPT), BLOCK), BLOCK, 0, a.s>>>(
         h->n_rows, h->ell.K, h->ell.pitch, h->ell.col.as<int32_t>(), h->ell.val.as<V>(),
         (const V *)a.x, (V)a.alpha, (V)a.beta, (V *)a.y);
     SPMV_CHECK_LAUNCH();
@@ -535,6 +628,20 @@ void ell_launch(const Args &a) {
                                       h->ell.val.as<V>(), a);
 }
 
+template <class V, int KS, int RPT>
+void ell_ksplit_launch(const Args &a) {
+    const spmv_matrix_s *h = a.h;
+    if (h->n_rows == 0) return;
+    if (h->nnz == 0) {  // masked gathers read x[0]; with no entries x may be empty
+        ell_launch<V, 1, 1>(a);
+        return;
+    }
+    ell_ksplit_kernel<V, KS, RPT><<<grid_of(ceil_div(h->n_rows, RPT), 64), 64 * KS, 0, a.s>>>(
+        h->n_rows, h->ell.K, h->ell.pitch, h->ell.col.as<int32_t>(), h->ell.val.as<V>(),
+        (const V *)a.x, (V)a.alpha, (V)a.beta, (V *)a.y);
+    SPMV_CHECK_LAUNCH();
+}
+
 template <class V, int RPT, int ITEMS>
 void hyb_launch(const Args &a) {
     const spmv_matrix_s *h = a.h;
@@ -547,13 +654,15 @@ void hyb_launch(const Args &a) {
 }
 
 #define V2(kind, blk, lanes, unr, fn) \
-    Variant{{kind, blk, lanes, unr, 1, 0}, fn<float>, fn<double>}
+    Variant{{kind, blk, lanes, unr, 1, 0, 1}, fn<float>, fn<double>}
 #define V4(kind, blk, lanes, unr, fn) \
-    Variant{{kind, blk, lanes, unr, 4, 0}, fn<float>, fn<double>}
+    Variant{{kind, blk, lanes, unr, 4, 0, 1}, fn<float>, fn<double>}
 #define VN(kind, blk, lanes, unr, vec, fn) \
-    Variant{{kind, blk, lanes, unr, vec, 0}, fn<float>, fn<double>}
+    Variant{{kind, blk, lanes, unr, vec, 0, 1}, fn<float>, fn<double>}
 #define VP(kind, blk, lanes, vec, pipe, fn) \
-    Variant{{kind, blk, lanes, 1, vec, pipe}, fn<float>, fn<double>}
+    Variant{{kind, blk, lanes, 1, vec, pipe, 1}, fn<float>, fn<double>}
+#define VK(kind, blk, rpt, ks, fn) \
+    Variant{{kind, blk, rpt, 1, rpt, 1, ks}, fn<float>, fn<double>}
 
 template <class V> void csr_s1(const Args &a) { csr_scalar_launch<V, 1>(a); }
 template <class V> void csr_s4(const Args &a) { csr_scalar_launch<V, 4>(a); }
@@ -584,9 +693,15 @@ CSRP(16, 2) CSRP(16, 4)
 CSRP(32, 2) CSRP(32, 4)
 CSRP(64, 2) CSRP(64, 4)
 #undef CSRP
-template <class V> void ell_p1(const Args &a) { ell_pipe_launch<V, 1>(a); }
-template <class V> void ell_p2(const Args &a) { ell_pipe_launch<V, 2>(a); }
-template <class V> void ell_p4(const Args &a) { ell_pipe_launch<V, 4>(a); }
+template <class V> void ell_p1(const Args &a) { ell_pipe_launch<V, 1, 1>(a); }
+template <class V> void ell_p2(const Args &a) { ell_pipe_launch<V, 2, 1>(a); }
+template <class V> void ell_p4(const Args &a) { ell_pipe_launch<V, 4, 1>(a); }
+template <class V> void ell_q2(const Args &a) { ell_pipe_launch<V, 2, 2>(a); }
+template <class V> void ell_q4(const Args &a) { ell_pipe_launch<V, 4, 2>(a); }
+template <class V> void ell_k2_2(const Args &a) { ell_ksplit_launch<V, 2, 2>(a); }
+template <class V> void ell_k4_1(const Args &a) { ell_ksplit_launch<V, 4, 1>(a); }
+template <class V> void ell_k4_2(const Args &a) { ell_ksplit_launch<V, 4, 2>(a); }
+template <class V> void ell_k4_4(const Args &a) { ell_ksplit_launch<V, 4, 4>(a); }
 template <class V> void coo_2(const Args &a) { coo_launch<V, 2>(a); }
 template <class V> void coo_4(const Args &a) { coo_launch<V, 4>(a); }
 template <class V> void coo_8(const Args &a) { coo_launch<V, 8>(a); }
@@ -659,6 +774,9 @@ const std::vector<Variant> &table(spmv_format f) {
         VN(SPMV_KERNEL_ELL, 256, 4, 1, 4, ell_4_1), VN(SPMV_KERNEL_ELL, 256, 4, 2, 4, ell_4_2),
         VP(SPMV_KERNEL_ELL, 256, 1, 1, 1, ell_p1), VP(SPMV_KERNEL_ELL, 256, 2, 2, 1, ell_p2),
         VP(SPMV_KERNEL_ELL, 256, 4, 4, 1, ell_p4),
+        VP(SPMV_KERNEL_ELL, 256, 2, 2, 2, ell_q2), VP(SPMV_KERNEL_ELL, 256, 4, 4, 2, ell_q4),
+        VK(SPMV_KERNEL_ELL, 128, 2, 2, ell_k2_2), VK(SPMV_KERNEL_ELL, 256, 1, 4, ell_k4_1),
+        VK(SPMV_KERNEL_ELL, 256, 2, 4, ell_k4_2), VK(SPMV_KERNEL_ELL, 256, 4, 4, ell_k4_4),
     };
     static const std::vector<Variant> hyb = {
         VN(SPMV_KERNEL_HYB, 256, 1, 4, 1, hyb_1_4), VN(SPMV_KERNEL_HYB, 256, 1, 8, 1, hyb_1_8),

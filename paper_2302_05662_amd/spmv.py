@@ -52,7 +52,7 @@ class SpmvError(RuntimeError):
 class spmv_variant_info(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("lanes", ctypes.c_int32), ("unroll", ctypes.c_int32), ("vec", ctypes.c_int32),
-                ("pipelined", ctypes.c_int32)]
+                ("pipelined", ctypes.c_int32), ("ksplit", ctypes.c_int32)]
 
 
 class spmv_arrays(ctypes.Structure):
@@ -234,7 +234,7 @@ def spmv_variant_describe(fmt: int, dtype_code: int, idx: int) -> dict:
     _check(_lib.spmv_variant_describe(int(fmt), int(dtype_code), int(idx), ctypes.byref(v)),
            "spmv_variant_describe")
     return {"kernel": KERNEL_NAMES[v.kernel], "block": v.block, "lanes": v.lanes,
-            "unroll": v.unroll, "vec": v.vec, "pipelined": v.pipelined}
+            "unroll": v.unroll, "vec": v.vec, "pipelined": v.pipelined, "ksplit": v.ksplit}
 
 
 def spmv_set_variant(h: Handle, fmt: int, idx: int):
@@ -359,14 +359,16 @@ def spmv_selector_get_weights() -> np.ndarray:
 class spmv_batch_config(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("unroll", ctypes.c_int32),
                 ("passes_per_tile", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("lanes_divisor", ctypes.c_int32), ("total_tiles", ctypes.c_int32),
-                ("grid", ctypes.c_int32), ("tuned_ms", ctypes.c_float)]
+                ("lanes_divisor", ctypes.c_int32), ("tiling", ctypes.c_int32),
+                ("total_tiles", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("tuned_ms", ctypes.c_float)]
 
 
 _sig("spmv_batch_create", _I32, ctypes.POINTER(_P), _P, _I32, _P, _P, _P, _P, ctypes.c_int, _P)
 _sig("spmv_batch_run", _I32, _P, _P)
 _sig("spmv_batch_update", _I32, _P, _P, _P, _P, _P, _P)
 _sig("spmv_batch_get_config", _I32, _P, ctypes.POINTER(spmv_batch_config), _P)
+_sig("spmv_batch_set_config", _I32, _P, ctypes.POINTER(spmv_batch_config), _P)
 _sig("spmv_batch_destroy", None, _P)
 
 
@@ -428,6 +430,15 @@ def spmv_batch_get_config(b: Batch):
     _check(_lib.spmv_batch_get_config(b.ptr, ctypes.byref(c), ctypes.c_void_p(lanes.ctypes.data)),
            "spmv_batch_get_config")
     return {f: getattr(c, f) for f, _ in c._fields_}, lanes
+
+
+def spmv_batch_set_config(b: Batch, stream=None, **setting):
+    """Rebuild the batch's graph with the given setting (keys of spmv_batch_config)."""
+    cur, _ = spmv_batch_get_config(b)
+    cur.update(setting)
+    c = spmv_batch_config(**{f: cur[f] for f, _ in spmv_batch_config._fields_})
+    _check(_lib.spmv_batch_set_config(b.ptr, ctypes.byref(c), _stream_ptr(stream)),
+           "spmv_batch_set_config")
 
 
 def spmv_batch_destroy(b: Batch):

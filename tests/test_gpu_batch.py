@@ -23,6 +23,7 @@ def _matrices():
     ms.append(synth.from_coords("empty_rows", 300, 200, [5, 5, 299], [0, 7, 199], 9))
     ms.append(synth.from_coords("no_entries", 50, 50, [], [], 10))
     ms.append(synth.random_rect(10, 4000, 9000, 11))  # ten rows of ~900 entries
+    ms.append(synth.power_law(3000, 12, cap=3000, value_dist="uniform"))  # rows past 2048
     return ms
 
 
@@ -61,20 +62,30 @@ def test_batch_matches_oracle_and_single_launches(dtype, tune):
     ms, hs, xs, ys, refs, y0s, alphas, betas = _setup(dtype, 21)
     print(f"[batch] {len(ms)} matrices {dtype.__name__} tune={tune}", flush=True)
     b = S.spmv_batch_create(hs, xs, ys, alphas, betas, tune=tune)
-    cfg, lanes = S.spmv_batch_get_config(b)
-    assert cfg["total_tiles"] > 0 and cfg["grid"] > 0
-    S.spmv_batch_run(b)
-    torch.cuda.synchronize()
     tol = 1e-5 if dtype == np.float32 else 1e-12
-    for i, m in enumerate(ms):
-        got = ys[i].cpu().numpy()
-        assert OS.max_row_error(got, *refs[i]) <= tol, m.name
-        # bit-equal to the single CSR vector launch with the same lanes and unroll
-        var = _single_variant(hs[i].dtype_code, int(lanes[i]), cfg["unroll"])
-        S.spmv_set_variant(hs[i], S.SPMV_FMT_CSR, var)
-        ys_single = torch.from_numpy(y0s[i].copy()).cuda()
-        S.spmv_run(hs[i], S.SPMV_FMT_CSR, alphas[i], xs[i], betas[i], ys_single)
-        assert ys_single.cpu().numpy().tobytes() == got.tobytes(), m.name
+    settings = [None, dict(tiling=1, unroll=2, passes_per_tile=1, lanes_divisor=2),
+                dict(tiling=0, unroll=1), dict(tiling=0, unroll=2, passes_per_tile=16)]
+    for setting in settings:
+        if setting is not None:
+            S.spmv_batch_set_config(b, **setting)
+        cfg, lanes = S.spmv_batch_get_config(b)
+        assert cfg["total_tiles"] > 0 and cfg["grid"] > 0
+        for i in range(len(ms)):
+            ys[i].copy_(torch.from_numpy(y0s[i]))
+        S.spmv_batch_run(b)
+        torch.cuda.synchronize()
+        for i, m in enumerate(ms):
+            got = ys[i].cpu().numpy()
+            assert OS.max_row_error(got, *refs[i]) <= tol, (setting, m.name)
+            if cfg["tiling"] != 0:
+                continue
+            # per-matrix tiling: bit-equal to the single CSR vector launch with the
+            # same lanes and unroll
+            var = _single_variant(hs[i].dtype_code, int(lanes[i]), cfg["unroll"])
+            S.spmv_set_variant(hs[i], S.SPMV_FMT_CSR, var)
+            ys_single = torch.from_numpy(y0s[i].copy()).cuda()
+            S.spmv_run(hs[i], S.SPMV_FMT_CSR, alphas[i], xs[i], betas[i], ys_single)
+            assert ys_single.cpu().numpy().tobytes() == got.tobytes(), (setting, m.name)
 
 
 def test_graph_replays_with_new_vectors_and_eager_work_between():
