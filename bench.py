@@ -112,6 +112,58 @@ def trace_summary(trace_csv, bench_json):
           f"(bench: {rf['achieved']} GB/s)")
 
 
+def counter_summary(fetch_csv, write_csv, bench_json, out_json):
+    """HBM bytes per launch of the roofline kernel from two rocprofv3 --pmc runs.
+
+    Both runs time the same plan; the counters of the kernel's last ``launches``
+    dispatches (the timed steps) are averaged, and each counter is scaled by what
+    it reads for the device copy of known size that ends the run.
+    """
+    import csv
+
+    with open(bench_json) as fh:
+        line = [l for l in fh if l.startswith("{")][-1]
+    res = json.loads(line)
+    rf, mib = res["roofline"], res["copy_calibration_mib"]
+    sym, n = rf["kernel_symbol"], rf["launches"]
+
+    def read(path, counter):
+        with open(path) as fh:
+            rows = [r for r in csv.DictReader(fh) if r["Counter_Name"] == counter]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        kern = [float(r["Counter_Value"]) for r in rows if sym in r["Kernel_Name"]][-n:]
+        copy = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]][-3:]
+        if min(copy, default=0.0) < mib * 1024.0 / 4:
+            raise SystemExit(f"{path}: the last device copies are not the {mib} MiB calibration")
+        if len(kern) != n or len(copy) != 3:
+            raise SystemExit(f"{path}: {len(kern)} dispatches of {sym} (want {n}), "
+                             f"{len(copy)} calibration copies (want 3)")
+        return sum(kern) / n, sum(copy) / 3
+
+    fetch, fetch_copy = read(fetch_csv, "FETCH_SIZE")
+    write, write_copy = read(write_csv, "WRITE_SIZE")
+    known_kib = mib * 1024.0
+    fs, ws = known_kib / fetch_copy, known_kib / write_copy
+    traffic = (fetch * fs + write * ws) * 1024.0
+    d = {"kernel_source_hash": kernel_source_hash(),
+         "note": "HBM bytes per launch over the timed steps: FETCH_SIZE x fetch scale + "
+                 "WRITE_SIZE x write scale (KiB x 1024)",
+         "fetch_scale": round(fs, 6), "write_scale": round(ws, 6),
+         "kernels": {rf["kernel"]: round(traffic)}}
+    with open(out_json, "w") as fh:
+        json.dump(d, fh, indent=1)
+        fh.write("\n")
+    print(f"kernel: {sym} ({rf['kernel']}), {n} timed dispatches")
+    print(f"| FETCH_SIZE per launch (raw) | {fetch:.1f} KiB |")
+    print(f"| WRITE_SIZE per launch (raw) | {write:.1f} KiB |")
+    print(f"| calibration: {mib} MiB device copy (3 runs) | FETCH {fetch_copy:.1f} KiB, "
+          f"WRITE {write_copy:.1f} KiB |")
+    print(f"| scale factors (known bytes / counter) | fetch {fs:.4f}, write {ws:.4f} |")
+    print(f"| HBM traffic per launch (scaled) | {traffic / 1e6:.1f} MB |")
+    print(f"| algorithmic bytes per launch | {rf['bytes_per_launch'] / 1e6:.1f} MB |")
+    print(f"| traffic / algorithmic | {traffic / rf['bytes_per_launch']:.3f} |")
+
+
 def cpu_baseline(mats, budget_s, threads):
     """The FP64 oracle's CSR SpMV on the host, over the first matrices until the budget is used."""
     from oracle import spmv as OS
@@ -282,9 +334,16 @@ def main():
                     help="after the timed steps, copy MIB MiB three times (counter calibration)")
     ap.add_argument("--trace-summary", nargs=2, metavar=("KERNEL_TRACE_CSV", "BENCH_JSON"),
                     help="summarise a rocprofv3 kernel trace of a previous run and exit")
+    ap.add_argument("--counter-summary", nargs=4,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON", "OUT_JSON"),
+                    help="HBM traffic of the roofline kernel from rocprofv3 FETCH_SIZE and "
+                         "WRITE_SIZE runs of a --copy-calibration bench; writes OUT_JSON and exits")
     args = ap.parse_args()
     if args.trace_summary:
         trace_summary(*args.trace_summary)
+        return
+    if args.counter_summary:
+        counter_summary(*args.counter_summary)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
@@ -372,21 +431,40 @@ def main():
             if events is not None:
                 events[i][1].record(stream)
 
+    # Everything else that launches kernels runs before the timed region, so the
+    # timed launches are the last SpMV dispatches of the run (a kernel trace's last
+    # `launches` dispatches of the roofline kernel are exactly the timed ones).
+    selector = selector_section(S, torch, mats, step, args.steps)
+    setup_rates = {
+        "ingest_nnz_per_s": round(total_nnz_of(mats) / sum(e["t_ingest"] for e in mats), 0),
+        "features_nnz_per_s": round(total_nnz_of(mats) / sum(e["t_feat"] for e in mats), 0),
+        "convert_ell_hyb_nnz_per_s": round(
+            2 * total_nnz_of(mats) / sum(e["t_ell"] + e["t_hyb"] for e in mats), 0),
+        "note": "host wall clock around each synchronous call, COO already in HBM; the paper's "
+                "CPU figures are about 4.8e5 (features) and 4.3e5 (conversion) nnz/s",
+    }
+    setup_rates.update(ingest_unsorted(S, torch, synth))
+    batched = None if args.no_batched else batched_section(S, torch, synth,
+                                                           args.batched_matrices)
+
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     per_launch = [[0.0, 0] for _ in mats]
+    # events for every launch of every step exist before the clock starts; the host
+    # enqueues all K steps without waiting, so launch overhead overlaps the kernels
+    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in mats] for _ in range(args.steps)]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in mats]
-        step(ev)
-        torch.cuda.synchronize()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for ev in evs:
         for i, (a, b) in enumerate(ev):
             per_launch[i][0] += a.elapsed_time(b)
             per_launch[i][1] += 1
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     if args.copy_calibration:
         src = torch.zeros(args.copy_calibration * 2**18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -433,19 +511,6 @@ def main():
             d["large_gbps"] = round(lb / lt / 1e9, 1)
         per_format[FMT_NAMES[fmt]] = d
     chosen = {FMT_NAMES[f]: sum(1 for e in mats if e["fmt"] == f) for f in range(4)}
-
-    selector = selector_section(S, torch, mats, step, args.steps)
-    setup_rates = {
-        "ingest_nnz_per_s": round(total_nnz_of(mats) / sum(e["t_ingest"] for e in mats), 0),
-        "features_nnz_per_s": round(total_nnz_of(mats) / sum(e["t_feat"] for e in mats), 0),
-        "convert_ell_hyb_nnz_per_s": round(
-            2 * total_nnz_of(mats) / sum(e["t_ell"] + e["t_hyb"] for e in mats), 0),
-        "note": "host wall clock around each synchronous call, COO already in HBM; the paper's "
-                "CPU figures are about 4.8e5 (features) and 4.3e5 (conversion) nnz/s",
-    }
-    setup_rates.update(ingest_unsorted(S, torch, synth))
-    batched = None if args.no_batched else batched_section(S, torch, synth,
-                                                           args.batched_matrices)
 
     cpu = None
     if not args.no_cpu:
@@ -494,6 +559,7 @@ def main():
             "bytes_per_launch": round(dom["bytes"] / dom["launches"], 1),
         },
         "cpu_baseline": cpu,
+        "copy_calibration_mib": args.copy_calibration,
         "per_format_tuned_cold": per_format,
         "selected_formats": chosen,
         "setup_s": round(setup_s, 1),

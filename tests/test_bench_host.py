@@ -50,3 +50,35 @@ def test_trace_summary_uses_the_last_timed_launches(tmp_path, capsys):
     out = capsys.readouterr().out
     assert "timed-region dispatches used: 4" in out
     assert "2.000 us" in out and "2000.0 GB/s" in out
+
+
+def _counter_csv(path, counter, rows):
+    fields = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=fields)
+        w.writeheader()
+        for i, (name, value) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i + 1, "Kernel_Name": name, "Counter_Name": counter,
+                        "Counter_Value": value})
+
+
+def test_counter_summary_scales_by_the_calibration_copy(tmp_path, capsys):
+    k = "void spmv::csr_vector4_kernel<float, 256, 16, 2>(int)"
+    copy = "__amd_rocclr_copyBuffer"
+    # a tuning dispatch, then 2 timed dispatches, then three 4 MiB calibration copies;
+    # the FETCH counter reads half of the true bytes, WRITE reads them exactly
+    _counter_csv(tmp_path / "f.csv", "FETCH_SIZE",
+                 [(k, 9999.0), (k, 1000.0), (k, 3000.0)] + [(copy, 2048.0)] * 3)
+    _counter_csv(tmp_path / "w.csv", "WRITE_SIZE",
+                 [(k, 9999.0), (k, 100.0), (k, 300.0)] + [(copy, 4096.0)] * 3)
+    (tmp_path / "b.json").write_text(json.dumps({
+        "copy_calibration_mib": 4,
+        "roofline": {"kernel": "csr_key", "kernel_symbol": "csr_vector4_kernel<float, 256, 16, 2>",
+                     "launches": 2, "bytes_per_launch": 4.0e6}}) + "\n")
+    bench.counter_summary(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"),
+                          str(tmp_path / "b.json"), str(tmp_path / "t.json"))
+    t = json.loads((tmp_path / "t.json").read_text())
+    assert t["fetch_scale"] == 2.0 and t["write_scale"] == 1.0
+    assert t["kernels"]["csr_key"] == (2000.0 * 2.0 + 200.0) * 1024
+    assert t["kernel_source_hash"] == bench.kernel_source_hash()
+    assert "traffic / algorithmic" in capsys.readouterr().out
