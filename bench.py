@@ -48,7 +48,7 @@ def format_bytes(fmt, n_rows, n_cols, nnz, vb, K=0, pitch=0, tail=0):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "common.hpp"):
+    for f in ("kernels.hip", "panel.hip", "device.hpp", "common.hpp"):
         with open(os.path.join(ROOT, "paper_2302_05662_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -81,6 +81,8 @@ def kernel_symbols(fmt, info, dtype="float"):
     if info["kernel"] == "csr_vector":
         name = "csr_vector4_kernel" if v == 4 else "csr_vector_kernel"
         return [f"{name}<{dtype}, {b}, {l}, {u}>"]
+    if info["kernel"] == "coo_panel":
+        return [f"coo_panel_kernel<{dtype}, {l}, true>"]
     if info["kernel"] == "coo":
         return [f"coo_tile_kernel<{dtype}, {b}, {l}, false>", f"coo_fixup<{dtype}, {b * l}, false>"]
     if info["kernel"] == "ell":

@@ -59,7 +59,11 @@ typedef enum spmv_kernel {
     SPMV_KERNEL_CSR_VECTOR = 1, /* `lanes` lanes of a wavefront per row           */
     SPMV_KERNEL_COO = 2,        /* nnz tiles, segmented reduction by row          */
     SPMV_KERNEL_ELL = 3,        /* `lanes` consecutive rows per thread            */
-    SPMV_KERNEL_HYB = 4         /* ELL part (`lanes` rows/thread) + COO tail      */
+    SPMV_KERNEL_HYB = 4,        /* ELL part (`lanes` rows/thread) + COO tail      */
+    SPMV_KERNEL_COO_PANEL = 5   /* COO entries in row-block x column-panel order,
+                                   x panels staged in LDS, one row group per wave;
+                                   needs a second copy of the entries, built by
+                                   spmv_set_variant / spmv_tune / spmv_time       */
 } spmv_kernel;
 
 typedef enum spmv_select_mode {

@@ -12,7 +12,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libspmv.so")
 SOURCES = ("api.hip", "ingest.hip", "convert.hip", "kernels.hip", "features.hip", "timing.hip",
-           "mlp.hip", "batch.hip")
+           "mlp.hip", "batch.hip", "panel.hip")
 ARCH = os.environ.get("SPMV_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -126,6 +126,18 @@ spmv_format select_rule(const float f[12], float votes[4]) {
 
 }  // namespace
 
+bool prepare_variant(spmv_matrix_s *h, spmv_format f, int32_t idx, hipStream_t s) {
+    if (!variant_needs_panel(f, idx) || h->panel.built) return true;
+    try {
+        build_panel(h, s);
+    } catch (const Error &e) {
+        if (e.status != SPMV_ERR_NOT_APPLICABLE) throw;
+        clear_error();
+        return false;
+    }
+    return true;
+}
+
 spmv_status select_model(spmv_matrix_s *h, const float feats[12], spmv_format *out, float scores[4],
                          hipStream_t s);  // mlp.hip
 
@@ -221,6 +233,8 @@ extern "C" spmv_status spmv_set_variant(spmv_handle h, spmv_format f, int32_t id
     return guard([&] {
         if (!h || !valid_format(f)) fail(SPMV_ERR_INVALID_ARG, "bad handle or format");
         if (idx < 0 || idx >= variant_count(f, h->dt)) fail(SPMV_ERR_INVALID_ARG, "bad variant %d", idx);
+        if (!prepare_variant(h, f, idx, nullptr))
+            fail(SPMV_ERR_NOT_APPLICABLE, "variant %d does not apply to this matrix", idx);
         h->variant[f] = idx;
     });
 }

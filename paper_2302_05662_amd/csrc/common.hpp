@@ -107,6 +107,28 @@ struct HybPart {
     DevBuf ell_col, ell_val, tail_row, tail_col, tail_val, partials;
 };
 
+// Row-block x column-panel copy of the entries for the panel SpMV kernel.
+// Rows are split into groups of `rows_per_wave` (one group per wavefront, 16
+// groups per workgroup) and columns into panels of panel_width() entries (64 KB
+// of x, staged in LDS). Entries are stored group by group, panel by panel, in
+// (row, col) order inside each (group, panel) run; every run is padded to a
+// multiple of 4 with index kPanelPad and value 0. An index packs the row inside
+// its group (high 16 bits) and the column inside its panel (low 16 bits).
+//   run_ptr[g * (panels + 1) + p]: start of run (g, p); [.. + panels]: end of
+//   group g's entries. blk_ptr[b] .. blk_ptr[b + 1]: the panels (ascending, in
+//   blk_panel) in which workgroup b's 16 groups hold at least one entry.
+constexpr int kPanelWaves = 16;
+constexpr int kPanelRowsMax = 512;
+constexpr int32_t kPanelPad = -1;
+inline int32_t panel_width(spmv_dtype dt) { return dt == SPMV_F64 ? 8192 : 16384; }
+
+struct PanelPart {
+    bool built = false;
+    int32_t rows_per_wave = 0, blocks = 0, panels = 0;
+    int64_t stream = 0;  // padded entries
+    DevBuf idx, val, run_ptr, blk_ptr, blk_panel;
+};
+
 // Row-length statistics kept from ingest (used by defaults and features).
 struct RowStats {
     int32_t max_len = 0;
@@ -125,6 +147,7 @@ struct spmv_matrix_s {
     spmv::DevBuf coo_partials;  // per-tile carries of the COO kernel
     spmv::EllPart ell;
     spmv::HybPart hyb;
+    spmv::PanelPart panel;  // built on first use of a panel variant of COO
     spmv::RowStats stats;
     int32_t variant[SPMV_NUM_FORMATS] = {0, 0, 0, 0};
 };
@@ -135,6 +158,9 @@ namespace spmv {
 
 // ingest.hip
 void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s);
+// Stable LSD radix sort of n 64-bit keys (the low `bits` bits) carrying a
+// 32-bit payload; on return `keys` and `payload` hold the sorted pairs.
+void radix_sort_pairs(DevBuf &keys, DevBuf &payload, int64_t n, int bits, hipStream_t s);
 int32_t device_max_row_len(const int32_t *row_ptr, int32_t n_rows, hipStream_t s);
 
 // convert.hip
@@ -142,10 +168,19 @@ void build_ell(spmv_matrix_s *h, hipStream_t s);
 void build_hyb(spmv_matrix_s *h, int32_t hyb_k, hipStream_t s);
 int32_t hyb_rule_width(spmv_matrix_s *h, hipStream_t s);
 
+// panel.hip
+void build_panel(spmv_matrix_s *h, hipStream_t s);  // NOT_APPLICABLE past the index limits
+void panel_spmv(const spmv_matrix_s *h, int items, double alpha, const void *x, double beta,
+                void *y, hipStream_t s);
+
 // kernels.hip
 int32_t variant_count(spmv_format f, spmv_dtype dt);
 bool variant_describe(spmv_format f, spmv_dtype dt, int32_t idx, spmv_variant_info *out);
 int32_t default_variant(const spmv_matrix_s *h, spmv_format f);
+bool variant_needs_panel(spmv_format f, int32_t idx);
+// Make variant idx of f runnable: builds the panel layout for a panel variant.
+// Returns false when that layout is not applicable to the matrix.
+bool prepare_variant(spmv_matrix_s *h, spmv_format f, int32_t idx, hipStream_t s);
 void launch_spmv(const spmv_matrix_s *h, spmv_format f, int32_t variant, double alpha,
                  const void *x, double beta, void *y, hipStream_t s);
 int64_t coo_partials_bytes(int64_t nnz, spmv_dtype dt);

@@ -252,37 +252,21 @@ void sort_into_handle(spmv_matrix_s *h, const int32_t *row, const int32_t *col, 
     const uint64_t span = (uint64_t)std::max(h->n_rows, 1) * (uint64_t)std::max(h->n_cols, 1);
     int bits = 0;
     while (bits < 64 && (span - 1) >> bits) ++bits;
-    const int passes = (bits + 7) / 8;
-    DevBuf k0, k1, i0, i1, hist;
-    k0.alloc(nnz * 8);
-    k1.alloc(nnz * 8);
-    i0.alloc(nnz * 4);
-    i1.alloc(nnz * 4);
-    const int n_tiles = (int)ceil_div(nnz, kTile);
-    hist.alloc((int64_t)256 * n_tiles * 4);
-    make_keys<<<grid_for(nnz), kBlock, 0, s>>>(row, col, nnz, h->n_cols, k0.as<uint64_t>(),
-                                               i0.as<uint32_t>());
+    DevBuf keys, perm;
+    keys.alloc(nnz * 8);
+    perm.alloc(nnz * 4);
+    make_keys<<<grid_for(nnz), kBlock, 0, s>>>(row, col, nnz, h->n_cols, keys.as<uint64_t>(),
+                                               perm.as<uint32_t>());
     SPMV_CHECK_LAUNCH();
-    uint64_t *kin = k0.as<uint64_t>(), *kout = k1.as<uint64_t>();
-    uint32_t *iin = i0.as<uint32_t>(), *iout = i1.as<uint32_t>();
-    for (int p = 0; p < passes; ++p) {
-        radix_hist<<<n_tiles, kBlock, 0, s>>>(kin, nnz, 8 * p, hist.as<int32_t>(), n_tiles);
-        SPMV_CHECK_LAUNCH();
-        exclusive_scan_i32(hist.as<int32_t>(), hist.as<int32_t>(), (int64_t)256 * n_tiles, s);
-        radix_scatter<<<n_tiles, kBlock, 0, s>>>(kin, iin, kout, iout, nnz, 8 * p,
-                                                 hist.as<int32_t>(), n_tiles);
-        SPMV_CHECK_LAUNCH();
-        std::swap(kin, kout);
-        std::swap(iin, iout);
-    }
+    radix_sort_pairs(keys, perm, nnz, bits, s);
     if (h->dt == SPMV_F64)
         gather_entries<double><<<grid_for(nnz), kBlock, 0, s>>>(
-            iin, row, col, (const double *)val, nnz, h->row.as<int32_t>(), h->col.as<int32_t>(),
-            h->val.as<double>());
+            perm.as<uint32_t>(), row, col, (const double *)val, nnz, h->row.as<int32_t>(),
+            h->col.as<int32_t>(), h->val.as<double>());
     else
         gather_entries<float><<<grid_for(nnz), kBlock, 0, s>>>(
-            iin, row, col, (const float *)val, nnz, h->row.as<int32_t>(), h->col.as<int32_t>(),
-            h->val.as<float>());
+            perm.as<uint32_t>(), row, col, (const float *)val, nnz, h->row.as<int32_t>(),
+            h->col.as<int32_t>(), h->val.as<float>());
     SPMV_CHECK_LAUNCH();
     SPMV_HIP(hipStreamSynchronize(s));
 }
@@ -290,6 +274,29 @@ void sort_into_handle(spmv_matrix_s *h, const int32_t *row, const int32_t *col, 
 }  // namespace
 
 // ---- shared helpers ------------------------------------------------------------
+
+void radix_sort_pairs(DevBuf &keys, DevBuf &payload, int64_t n, int bits, hipStream_t s) {
+    const int passes = (bits + 7) / 8;
+    if (n <= 1 || passes == 0) return;
+    DevBuf k1, p1, hist;
+    k1.alloc(n * 8);
+    p1.alloc(n * 4);
+    const int n_tiles = (int)ceil_div(n, kTile);
+    hist.alloc((int64_t)256 * n_tiles * 4);
+    for (int p = 0; p < passes; ++p) {
+        radix_hist<<<n_tiles, kBlock, 0, s>>>(keys.as<uint64_t>(), n, 8 * p, hist.as<int32_t>(),
+                                              n_tiles);
+        SPMV_CHECK_LAUNCH();
+        exclusive_scan_i32(hist.as<int32_t>(), hist.as<int32_t>(), (int64_t)256 * n_tiles, s);
+        radix_scatter<<<n_tiles, kBlock, 0, s>>>(keys.as<uint64_t>(), payload.as<uint32_t>(),
+                                                 k1.as<uint64_t>(), p1.as<uint32_t>(), n, 8 * p,
+                                                 hist.as<int32_t>(), n_tiles);
+        SPMV_CHECK_LAUNCH();
+        std::swap(keys, k1);
+        std::swap(payload, p1);
+    }
+    SPMV_HIP(hipStreamSynchronize(s));  // the temporaries are freed on return
+}
 
 void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s) {
     if (n <= 0) return;

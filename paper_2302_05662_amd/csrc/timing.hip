@@ -107,10 +107,16 @@ double tune_format(spmv_matrix_s *h, spmv_format f, const void *x, void *y, int3
     double best = INFINITY;
     int32_t bi = h->variant[f];
     for (int32_t v = 0; v < nv; ++v) {
+        if (!prepare_variant(h, f, v, s)) continue;
         const double m = median_of(time_runs(h, f, v, x, y, 2, reps, flush, s));
         if (m < best) { best = m; bi = v; }
     }
     h->variant[f] = bi;
+    // the panel copy of the entries is kept only while a panel variant is in use
+    if (h->panel.built && !variant_needs_panel(f, bi) && !variant_needs_panel(SPMV_FMT_COO, h->variant[SPMV_FMT_COO])) {
+        SPMV_HIP(hipStreamSynchronize(s));
+        h->panel = PanelPart{};
+    }
     if (best_idx) *best_idx = bi;
     return best;
 }
@@ -129,6 +135,8 @@ extern "C" spmv_status spmv_time(spmv_handle h, spmv_format f, int32_t variant, 
         if ((h->n_cols > 0 && !x) || (h->n_rows > 0 && !y)) fail(SPMV_ERR_INVALID_ARG, "NULL x or y");
         const int32_t v = variant < 0 ? h->variant[f] : variant;
         if (v >= variant_count(f, h->dt)) fail(SPMV_ERR_INVALID_ARG, "variant %d out of range", v);
+        if (!prepare_variant(h, f, v, (hipStream_t)stream))
+            fail(SPMV_ERR_NOT_APPLICABLE, "variant %d does not apply to this matrix", v);
         std::vector<float> ms = time_runs(h, f, v, x, y, warmup, reps, flush, (hipStream_t)stream);
         std::copy(ms.begin(), ms.end(), out_ms);
     });

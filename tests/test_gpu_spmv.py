@@ -154,3 +154,32 @@ def test_full_size_sampled_rows(which):
             err = OS.max_row_error(got, y_ref, den)
             assert err <= C.TOL[dtype], (S.FORMAT_NAMES[fmt], var, err)
             assert math.isfinite(err)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_panel_variants_with_unaligned_x(dtype):
+    """x that is not 16-byte aligned takes the element-wise panel loads; same result bit for bit."""
+    name = "wide"
+    m = C.matrix(name)
+    print(f"[spmv panel unaligned] {name} {dtype.__name__}", flush=True)
+    h = _create(name, dtype)
+    x, y0 = C.vectors(name, dtype)
+    xd = torch.from_numpy(x).cuda()
+    buf = torch.zeros(m.n_cols + 1, dtype=xd.dtype, device="cuda")
+    buf[1:] = xd
+    xu = buf[1:]
+    assert xu.data_ptr() % 16 != 0
+    a, b = C.ALPHA_BETA[1]
+    y_ref, den = C.reference(name, dtype, a, b)
+    panel = [v for v in range(S.spmv_variant_count(S.SPMV_FMT_COO, h.dtype_code))
+             if S.spmv_variant_describe(S.SPMV_FMT_COO, h.dtype_code, v)["kernel"] == "coo_panel"]
+    assert panel
+    for var in panel:
+        S.spmv_set_variant(h, S.SPMV_FMT_COO, var)
+        ya = torch.from_numpy(y0.copy()).cuda()
+        yu = torch.from_numpy(y0.copy()).cuda()
+        S.spmv_run(h, S.SPMV_FMT_COO, a, xd, b, ya)
+        S.spmv_run(h, S.SPMV_FMT_COO, a, xu, b, yu)
+        ga, gu = ya.cpu().numpy(), yu.cpu().numpy()
+        assert ga.tobytes() == gu.tobytes(), var
+        assert OS.max_row_error(ga, y_ref, den) <= C.TOL[dtype]
