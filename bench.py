@@ -82,7 +82,7 @@ def kernel_symbols(fmt, info, dtype="float"):
         name = "csr_vector4_kernel" if v == 4 else "csr_vector_kernel"
         return [f"{name}<{dtype}, {b}, {l}, {u}>"]
     if info["kernel"] == "coo_panel":
-        return [f"coo_panel_kernel<{dtype}, {l}, true>"]
+        return [f"coo_panel_kernel<{dtype}, {l}>"]
     if info["kernel"] == "coo":
         return [f"coo_tile_kernel<{dtype}, {b}, {l}, false>", f"coo_fixup<{dtype}, {b * l}, false>"]
     if info["kernel"] == "ell":
@@ -414,6 +414,12 @@ def main():
             var, ms = S.spmv_tune(h, fmt, xd, yd, reps=args.tune_reps, flush=True)
             entry["times"][fmt] = ms
             entry["variant"][fmt] = var
+        if entry["variant"].get(1, -1) >= 0 and \
+                S.spmv_variant_describe(1, S.SPMV_F32, entry["variant"][1])["kernel"] == "coo_panel":
+            # the streaming COO copy packs row and column in one index: 8 bytes per FP32
+            # entry plus one pointer per row group, priced like CSR (a small underestimate:
+            # each row group's stream is padded to a multiple of 4 entries)
+            entry["bytes"][1] = format_bytes(0, m.n_rows, m.n_cols, m.nnz, 4)
         for fmt in range(4):
             entry["variant"].setdefault(fmt, -1)
         entry["fmt"] = int(np.argmin([entry["times"][f] for f in range(4)]))

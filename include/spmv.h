@@ -60,10 +60,11 @@ typedef enum spmv_kernel {
     SPMV_KERNEL_COO = 2,        /* nnz tiles, segmented reduction by row          */
     SPMV_KERNEL_ELL = 3,        /* `lanes` consecutive rows per thread            */
     SPMV_KERNEL_HYB = 4,        /* ELL part (`lanes` rows/thread) + COO tail      */
-    SPMV_KERNEL_COO_PANEL = 5   /* COO entries in row-block x column-panel order,
-                                   x panels staged in LDS, one row group per wave;
-                                   needs a second copy of the entries, built by
-                                   spmv_set_variant / spmv_tune / spmv_time       */
+    SPMV_KERNEL_COO_PANEL = 5   /* COO entries of each row group (one per wave)
+                                   streamed in column-panel order, so an XCD's x
+                                   gathers stay in a window of x; needs a second
+                                   copy of the entries, built by spmv_set_variant
+                                   / spmv_tune / spmv_time; n_cols < 2^23 - 1     */
 } spmv_kernel;
 
 typedef enum spmv_select_mode {

@@ -114,12 +114,15 @@ spmv_format select_exhaustive(spmv_matrix_s *h, float scores[4], hipStream_t s) 
 
 // Fixed thresholds on the features (a baseline for the learned selector):
 // ELL when it pads little, HYB when a few rows are far longer than the rest
-// and its COO tail stays small, CSR otherwise.
+// and its COO tail stays small, COO when a large matrix spreads its columns
+// over most of x (the column-panel streaming COO kernel), CSR otherwise.
 spmv_format select_rule(const float f[12], float votes[4]) {
-    const double mean = f[2], ell_ratio = f[7], mx = f[8], tail = f[11];
+    const double n = f[0], nnz = f[1], mean = f[2], ell_ratio = f[7], mx = f[8], bw = f[9],
+                 tail = f[11];
     spmv_format r = SPMV_FMT_CSR;
     if (ell_ratio >= 0.9) r = SPMV_FMT_ELL;
     else if (mean > 0 && mx > 32 * mean && tail < 0.3) r = SPMV_FMT_HYB;
+    else if (n > 0 && bw > 0.5 * n && nnz >= 4e6) r = SPMV_FMT_COO;
     for (int i = 0; i < 4; ++i) votes[i] = (i == (int)r) ? 1.f : 0.f;
     return r;
 }

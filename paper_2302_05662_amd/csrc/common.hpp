@@ -107,26 +107,24 @@ struct HybPart {
     DevBuf ell_col, ell_val, tail_row, tail_col, tail_val, partials;
 };
 
-// Row-block x column-panel copy of the entries for the panel SpMV kernel.
-// Rows are split into groups of `rows_per_wave` (one group per wavefront, 16
-// groups per workgroup) and columns into panels of panel_width() entries (64 KB
-// of x, staged in LDS). Entries are stored group by group, panel by panel, in
-// (row, col) order inside each (group, panel) run; every run is padded to a
-// multiple of 4 with index kPanelPad and value 0. An index packs the row inside
-// its group (high 16 bits) and the column inside its panel (low 16 bits).
-//   run_ptr[g * (panels + 1) + p]: start of run (g, p); [.. + panels]: end of
-//   group g's entries. blk_ptr[b] .. blk_ptr[b + 1]: the panels (ascending, in
-//   blk_panel) in which workgroup b's 16 groups hold at least one entry.
-constexpr int kPanelWaves = 16;
-constexpr int kPanelRowsMax = 512;
+// Column-panel ordered copy of the COO entries for the streaming COO kernel.
+// Rows are split into groups of `rows_per_wave` consecutive rows, one group per
+// wavefront; a group's entries are stored contiguously, ordered by column panel
+// (kPanelWidth columns), then row, then column, and the group's stream is padded
+// to a multiple of 4 entries with index kPanelPad and value 0. An index packs
+// the row inside its group (high 9 bits) and the global column (low 23 bits).
+// group_ptr[g] .. group_ptr[g + 1] is group g's stream.
+constexpr int kPanelWaves = 8;        // wavefronts (row groups) per workgroup
+constexpr int kPanelRowsMax = 512;    // rows per group at most (LDS accumulators)
+constexpr int kPanelColBits = 23;     // columns below 2^23 - 1
+constexpr int32_t kPanelWidth = 16384;
 constexpr int32_t kPanelPad = -1;
-inline int32_t panel_width(spmv_dtype dt) { return dt == SPMV_F64 ? 8192 : 16384; }
 
 struct PanelPart {
     bool built = false;
-    int32_t rows_per_wave = 0, blocks = 0, panels = 0;
+    int32_t rows_per_wave = 0, blocks = 0;
     int64_t stream = 0;  // padded entries
-    DevBuf idx, val, run_ptr, blk_ptr, blk_panel;
+    DevBuf idx, val, group_ptr;
 };
 
 // Row-length statistics kept from ingest (used by defaults and features).
@@ -147,7 +145,7 @@ struct spmv_matrix_s {
     spmv::DevBuf coo_partials;  // per-tile carries of the COO kernel
     spmv::EllPart ell;
     spmv::HybPart hyb;
-    spmv::PanelPart panel;  // built on first use of a panel variant of COO
+    spmv::PanelPart panel;  // built on first use of a streaming COO variant
     spmv::RowStats stats;
     int32_t variant[SPMV_NUM_FORMATS] = {0, 0, 0, 0};
 };

@@ -705,8 +705,8 @@ template <class V> void ell_k4_4(const Args &a) { ell_ksplit_launch<V, 4, 4>(a);
 template <class V> void coo_2(const Args &a) { coo_launch<V, 2>(a); }
 template <class V> void coo_4(const Args &a) { coo_launch<V, 4>(a); }
 template <class V> void coo_8(const Args &a) { coo_launch<V, 8>(a); }
-template <class V> void coo_panel_2(const Args &a) { panel_spmv(a.h, 2, a.alpha, a.x, a.beta, a.y, a.s); }
 template <class V> void coo_panel_4(const Args &a) { panel_spmv(a.h, 4, a.alpha, a.x, a.beta, a.y, a.s); }
+template <class V> void coo_panel_8(const Args &a) { panel_spmv(a.h, 8, a.alpha, a.x, a.beta, a.y, a.s); }
 template <class V> void ell_1_1(const Args &a) { ell_launch<V, 1, 1>(a); }
 template <class V> void ell_1_2(const Args &a) { ell_launch<V, 1, 2>(a); }
 template <class V> void ell_2_1(const Args &a) { ell_launch<V, 2, 1>(a); }
@@ -769,8 +769,8 @@ const std::vector<Variant> &table(spmv_format f) {
         VN(SPMV_KERNEL_COO, 256, 2, 1, 2, coo_2),
         VN(SPMV_KERNEL_COO, 256, 4, 1, 4, coo_4),
         VN(SPMV_KERNEL_COO, 256, 8, 1, 4, coo_8),
-        VP(SPMV_KERNEL_COO_PANEL, 1024, 2, 2, 1, coo_panel_2),
-        VP(SPMV_KERNEL_COO_PANEL, 1024, 4, 4, 1, coo_panel_4),
+        VP(SPMV_KERNEL_COO_PANEL, 512, 4, 4, 1, coo_panel_4),
+        VP(SPMV_KERNEL_COO_PANEL, 512, 8, 4, 1, coo_panel_8),
     };
     static const std::vector<Variant> ell = {
         VN(SPMV_KERNEL_ELL, 256, 1, 1, 1, ell_1_1), VN(SPMV_KERNEL_ELL, 256, 1, 2, 1, ell_1_2),
