@@ -83,6 +83,8 @@ def kernel_symbols(fmt, info, dtype="float"):
         return [f"{name}<{dtype}, {b}, {l}, {u}>"]
     if info["kernel"] == "coo_panel":
         return [f"coo_panel_kernel<{dtype}, {l}>"]
+    if info["kernel"] == "coo_sorted":
+        return [f"coo_sorted_kernel<{dtype}, {l}>"]
     if info["kernel"] == "coo":
         return [f"coo_tile_kernel<{dtype}, {b}, {l}, false>", f"coo_fixup<{dtype}, {b * l}, false>"]
     if info["kernel"] == "ell":
@@ -415,10 +417,11 @@ def main():
             entry["times"][fmt] = ms
             entry["variant"][fmt] = var
         if entry["variant"].get(1, -1) >= 0 and \
-                S.spmv_variant_describe(1, S.SPMV_F32, entry["variant"][1])["kernel"] == "coo_panel":
-            # the streaming COO copy packs row and column in one index: 8 bytes per FP32
-            # entry plus one pointer per row group, priced like CSR (a small underestimate:
-            # each row group's stream is padded to a multiple of 4 entries)
+                S.spmv_variant_describe(1, S.SPMV_F32, entry["variant"][1])["kernel"] in (
+                    "coo_panel", "coo_sorted"):
+            # the reordered COO copies pack row and column in one index: 8 bytes per FP32
+            # entry plus one pointer per row group or block, priced like CSR (a small
+            # underestimate: each group's or block's stream is padded to 4 entries)
             entry["bytes"][1] = format_bytes(0, m.n_rows, m.n_cols, m.nnz, 4)
         for fmt in range(4):
             entry["variant"].setdefault(fmt, -1)
@@ -433,11 +436,12 @@ def main():
 
     def step(events=None, key="fmt"):
         for i, e in enumerate(mats):
-            if events is not None:
-                events[i][0].record(stream)
+            pair = events[i] if events is not None else None
+            if pair is not None:
+                pair[0].record(stream)
             S.spmv_run(e["h"], e[key], 1.0, e["xd"], 0.0, e["y"])
-            if events is not None:
-                events[i][1].record(stream)
+            if pair is not None:
+                pair[1].record(stream)
 
     # Everything else that launches kernels runs before the timed region, so the
     # timed launches are the last SpMV dispatches of the run (a kernel trace's last
@@ -455,24 +459,54 @@ def main():
     batched = None if args.no_batched else batched_section(S, torch, synth,
                                                            args.batched_matrices)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    per_launch = [[0.0, 0] for _ in mats]
-    # events for every launch of every step exist before the clock starts; the host
-    # enqueues all K steps without waiting, so launch overhead overlaps the kernels
-    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-            for _ in mats] for _ in range(args.steps)]
+    def group_key(e):
+        info = S.spmv_variant_describe(e["fmt"], S.SPMV_F32, e["variant"][e["fmt"]])
+        key = (f"{info['kernel']}_b{info['block']}_l{info['lanes']}_u{info['unroll']}"
+               f"_v{info['vec']}_p{info['pipelined']}_k{info['ksplit']}_f32")
+        return key, info
+
+    def new_events(n):
+        return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                for _ in range(n)]
+
+    # Warmup steps carry a pair of events on every launch: they give the kernel time per
+    # step and pick the roofline kernel, the (format, variant) group with the largest
+    # share of kernel time.
+    warm = [0.0 for _ in mats]
+    for _ in range(max(args.warmup, 1)):
+        ev = new_events(len(mats))
+        step(ev)
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(ev):
+            warm[i] += a.elapsed_time(b) / max(args.warmup, 1)
+    kernel_ms_per_step = sum(warm)
+    groups = {}
+    for i, e in enumerate(mats):
+        key, info = group_key(e)
+        g = groups.setdefault(key, {"warm_ms": 0.0, "members": [], "symbols": kernel_symbols(e["fmt"], info)})
+        g["warm_ms"] += warm[i]
+        g["members"].append(i)
+    dom_key = max(groups, key=lambda k: groups[k]["warm_ms"])
+    dom = groups[dom_key]
+    members = set(dom["members"])
+
+    # Timed steps: events only around the roofline kernel's launches; all K steps are
+    # enqueued without waiting, so launch overhead overlaps the kernels.
+    evs = [[new_events(1)[0] if i in members else None for i in range(len(mats))]
+           for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         step(evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    dom["ms"], dom["launches"], dom["bytes"] = 0.0, 0, 0.0
     for ev in evs:
-        for i, (a, b) in enumerate(ev):
-            per_launch[i][0] += a.elapsed_time(b)
-            per_launch[i][1] += 1
+        for i, pair in enumerate(ev):
+            if pair is not None:
+                dom["ms"] += pair[0].elapsed_time(pair[1])
+                dom["launches"] += 1
+                dom["bytes"] += mats[i]["bytes"][mats[i]["fmt"]]
     if args.copy_calibration:
         src = torch.zeros(args.copy_calibration * 2**18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -481,24 +515,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     ms_per_step = wall * 1e3 / args.steps
-    kernel_ms_per_step = sum(p[0] for p in per_launch) / args.steps
 
     useful = sum(e["useful_bytes"] for e in mats)
     value = useful / (ms_per_step * 1e-3) / 1e9
-
-    # dominant kernel: the (format, variant) with the largest share of kernel time
-    groups = {}
-    for e, (ms, cnt) in zip(mats, per_launch):
-        info = S.spmv_variant_describe(e["fmt"], S.SPMV_F32, e["variant"][e["fmt"]])
-        key = (f"{info['kernel']}_b{info['block']}_l{info['lanes']}_u{info['unroll']}"
-               f"_v{info['vec']}_p{info['pipelined']}_k{info['ksplit']}_f32")
-        g = groups.setdefault(key, {"ms": 0.0, "launches": 0, "bytes": 0.0,
-                                    "symbols": kernel_symbols(e["fmt"], info)})
-        g["ms"] += ms
-        g["launches"] += cnt
-        g["bytes"] += e["bytes"][e["fmt"]] * cnt
-    dom_key = max(groups, key=lambda k: groups[k]["ms"])
-    dom = groups[dom_key]
     achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
     traffic = load_traffic(dom_key)
 
@@ -559,7 +578,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": traffic,
-            "share_of_kernel_time": round(dom["ms"] / sum(g["ms"] for g in groups.values()), 3),
+            "share_of_kernel_time": round(dom["warm_ms"] / kernel_ms_per_step, 3),
             "kernel_symbol": dom["symbols"][0],
             "kernels_per_launch": len(dom["symbols"]),
             "launches": dom["launches"],

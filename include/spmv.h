@@ -60,11 +60,17 @@ typedef enum spmv_kernel {
     SPMV_KERNEL_COO = 2,        /* nnz tiles, segmented reduction by row          */
     SPMV_KERNEL_ELL = 3,        /* `lanes` consecutive rows per thread            */
     SPMV_KERNEL_HYB = 4,        /* ELL part (`lanes` rows/thread) + COO tail      */
-    SPMV_KERNEL_COO_PANEL = 5   /* COO entries of each row group (one per wave)
+    SPMV_KERNEL_COO_PANEL = 5,  /* COO entries of each row group (one per wave)
                                    streamed in column-panel order, so an XCD's x
                                    gathers stay in a window of x; needs a second
                                    copy of the entries, built by spmv_set_variant
                                    / spmv_tune / spmv_time; n_cols < 2^23 - 1     */
+    SPMV_KERNEL_COO_SORTED = 6  /* COO entries of each block of rows sorted by
+                                   column, so a wave's gathers share cache lines;
+                                   rows summed with LDS atomics across the block's
+                                   16 waves: the order of the FP64 additions, and
+                                   so the last bits of a result, may vary between
+                                   runs; second copy of the entries as above      */
 } spmv_kernel;
 
 typedef enum spmv_select_mode {

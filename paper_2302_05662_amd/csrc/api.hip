@@ -113,16 +113,15 @@ spmv_format select_exhaustive(spmv_matrix_s *h, float scores[4], hipStream_t s) 
 }
 
 // Fixed thresholds on the features (a baseline for the learned selector):
-// ELL when it pads little, HYB when a few rows are far longer than the rest
-// and its COO tail stays small, COO when a large matrix spreads its columns
-// over most of x (the column-panel streaming COO kernel), CSR otherwise.
+// HYB when a few rows are far longer than the rest and its COO tail stays
+// small, COO (the column-sorted block kernel) for large matrices with rows of
+// 16 or more entries, ELL when it pads little, CSR otherwise.
 spmv_format select_rule(const float f[12], float votes[4]) {
-    const double n = f[0], nnz = f[1], mean = f[2], ell_ratio = f[7], mx = f[8], bw = f[9],
-                 tail = f[11];
+    const double nnz = f[1], mean = f[2], ell_ratio = f[7], mx = f[8], tail = f[11];
     spmv_format r = SPMV_FMT_CSR;
-    if (ell_ratio >= 0.9) r = SPMV_FMT_ELL;
-    else if (mean > 0 && mx > 32 * mean && tail < 0.3) r = SPMV_FMT_HYB;
-    else if (n > 0 && bw > 0.5 * n && nnz >= 4e6) r = SPMV_FMT_COO;
+    if (mean > 0 && mx > 32 * mean && tail < 0.3) r = SPMV_FMT_HYB;
+    else if (mean >= 16 && nnz >= 4e6) r = SPMV_FMT_COO;
+    else if (ell_ratio >= 0.9) r = SPMV_FMT_ELL;
     for (int i = 0; i < 4; ++i) votes[i] = (i == (int)r) ? 1.f : 0.f;
     return r;
 }
@@ -130,9 +129,12 @@ spmv_format select_rule(const float f[12], float votes[4]) {
 }  // namespace
 
 bool prepare_variant(spmv_matrix_s *h, spmv_format f, int32_t idx, hipStream_t s) {
-    if (!variant_needs_panel(f, idx) || h->panel.built) return true;
+    const bool panel = variant_needs_panel(f, idx) && !h->panel.built;
+    const bool sorted = variant_needs_sorted(f, idx) && !h->sorted.built;
+    if (!panel && !sorted) return true;
     try {
-        build_panel(h, s);
+        if (panel) build_panel(h, s);
+        if (sorted) build_sorted(h, s);
     } catch (const Error &e) {
         if (e.status != SPMV_ERR_NOT_APPLICABLE) throw;
         clear_error();

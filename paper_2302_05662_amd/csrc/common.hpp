@@ -127,6 +127,22 @@ struct PanelPart {
     DevBuf idx, val, group_ptr;
 };
 
+// Column-sorted copy of the COO entries for the sorted-block COO kernel: rows
+// are cut into blocks of `rows` consecutive rows (one workgroup each); a block's
+// entries are stored contiguously sorted by column (then row) and padded to a
+// multiple of 4 with index kPanelPad and value 0. An index packs the row inside
+// the block above the column: (row % rows) << col_bits | col, with col_bits the
+// bit length of n_cols. blk_ptr[b] .. blk_ptr[b + 1] is block b's stream.
+constexpr int kSortedWaves = 16;     // wavefronts per workgroup
+constexpr int kSortedRowsMax = 4096; // rows per block at most (LDS accumulators)
+
+struct SortedPart {
+    bool built = false;
+    int32_t rows = 0, blocks = 0, col_bits = 0;
+    int64_t stream = 0;
+    DevBuf idx, val, blk_ptr;
+};
+
 // Row-length statistics kept from ingest (used by defaults and features).
 struct RowStats {
     int32_t max_len = 0;
@@ -145,7 +161,8 @@ struct spmv_matrix_s {
     spmv::DevBuf coo_partials;  // per-tile carries of the COO kernel
     spmv::EllPart ell;
     spmv::HybPart hyb;
-    spmv::PanelPart panel;  // built on first use of a streaming COO variant
+    spmv::PanelPart panel;    // built on first use of a streaming COO variant
+    spmv::SortedPart sorted;  // built on first use of a sorted-block COO variant
     spmv::RowStats stats;
     int32_t variant[SPMV_NUM_FORMATS] = {0, 0, 0, 0};
 };
@@ -170,12 +187,16 @@ int32_t hyb_rule_width(spmv_matrix_s *h, hipStream_t s);
 void build_panel(spmv_matrix_s *h, hipStream_t s);  // NOT_APPLICABLE past the index limits
 void panel_spmv(const spmv_matrix_s *h, int items, double alpha, const void *x, double beta,
                 void *y, hipStream_t s);
+void build_sorted(spmv_matrix_s *h, hipStream_t s);
+void sorted_spmv(const spmv_matrix_s *h, int items, double alpha, const void *x, double beta,
+                 void *y, hipStream_t s);
 
 // kernels.hip
 int32_t variant_count(spmv_format f, spmv_dtype dt);
 bool variant_describe(spmv_format f, spmv_dtype dt, int32_t idx, spmv_variant_info *out);
 int32_t default_variant(const spmv_matrix_s *h, spmv_format f);
 bool variant_needs_panel(spmv_format f, int32_t idx);
+bool variant_needs_sorted(spmv_format f, int32_t idx);
 // Make variant idx of f runnable: builds the panel layout for a panel variant.
 // Returns false when that layout is not applicable to the matrix.
 bool prepare_variant(spmv_matrix_s *h, spmv_format f, int32_t idx, hipStream_t s);

@@ -707,6 +707,8 @@ template <class V> void coo_4(const Args &a) { coo_launch<V, 4>(a); }
 template <class V> void coo_8(const Args &a) { coo_launch<V, 8>(a); }
 template <class V> void coo_panel_4(const Args &a) { panel_spmv(a.h, 4, a.alpha, a.x, a.beta, a.y, a.s); }
 template <class V> void coo_panel_8(const Args &a) { panel_spmv(a.h, 8, a.alpha, a.x, a.beta, a.y, a.s); }
+template <class V> void coo_sorted_4(const Args &a) { sorted_spmv(a.h, 4, a.alpha, a.x, a.beta, a.y, a.s); }
+template <class V> void coo_sorted_8(const Args &a) { sorted_spmv(a.h, 8, a.alpha, a.x, a.beta, a.y, a.s); }
 template <class V> void ell_1_1(const Args &a) { ell_launch<V, 1, 1>(a); }
 template <class V> void ell_1_2(const Args &a) { ell_launch<V, 1, 2>(a); }
 template <class V> void ell_2_1(const Args &a) { ell_launch<V, 2, 1>(a); }
@@ -771,6 +773,8 @@ const std::vector<Variant> &table(spmv_format f) {
         VN(SPMV_KERNEL_COO, 256, 8, 1, 4, coo_8),
         VP(SPMV_KERNEL_COO_PANEL, 512, 4, 4, 1, coo_panel_4),
         VP(SPMV_KERNEL_COO_PANEL, 512, 8, 4, 1, coo_panel_8),
+        VP(SPMV_KERNEL_COO_SORTED, 1024, 4, 4, 1, coo_sorted_4),
+        VP(SPMV_KERNEL_COO_SORTED, 1024, 8, 4, 1, coo_sorted_8),
     };
     static const std::vector<Variant> ell = {
         VN(SPMV_KERNEL_ELL, 256, 1, 1, 1, ell_1_1), VN(SPMV_KERNEL_ELL, 256, 1, 2, 1, ell_1_2),
@@ -840,6 +844,11 @@ int32_t default_variant(const spmv_matrix_s *h, spmv_format f) {
 bool variant_needs_panel(spmv_format f, int32_t idx) {
     const auto &t = table(f);
     return idx >= 0 && idx < (int32_t)t.size() && t[idx].info.kernel == SPMV_KERNEL_COO_PANEL;
+}
+
+bool variant_needs_sorted(spmv_format f, int32_t idx) {
+    const auto &t = table(f);
+    return idx >= 0 && idx < (int32_t)t.size() && t[idx].info.kernel == SPMV_KERNEL_COO_SORTED;
 }
 
 void launch_spmv(const spmv_matrix_s *h, spmv_format f, int32_t variant, double alpha,

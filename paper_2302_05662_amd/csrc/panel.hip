@@ -17,6 +17,16 @@
 // row can end two segments of a chunk, from two panels, so the add is a
 // local atomic). Row totals are written once at the end as
 // y = alpha * s + beta * y.
+//
+// The sorted-block COO kernel goes further: a workgroup owns a block of up to
+// 4096 rows whose entries are sorted by column, and its 16 wavefronts stream
+// equal slices of them. The 64 lanes of one gather then read nearby columns
+// and share cache lines (on a uniformly random matrix with ~33 entries per row
+// and 256 blocks, about 4 entries per 128-byte line of x), so a gather moves a
+// quarter of the lines a row-ordered kernel moves. Each product is added to
+// the row's FP64 accumulator in LDS with a local atomic; the order in which
+// the wavefronts' adds land is not fixed, so results may differ between runs
+// in the last bits of the FP64 sums (FP32 outputs almost never change).
 #include <algorithm>
 #include <climits>
 
@@ -188,7 +198,182 @@ void launch_panel(const spmv_matrix_s *h, double alpha, const void *x, double be
     SPMV_CHECK_LAUNCH();
 }
 
+// ---- sorted-block COO ------------------------------------------------------------
+
+constexpr int kST = kSortedWaves * kWave;
+
+template <class V, int ITEMS>
+__global__ __launch_bounds__(kST) void coo_sorted_kernel(
+    int32_t n_rows, int32_t rows, int32_t col_bits, const int32_t *__restrict__ blk_ptr,
+    const int32_t *__restrict__ idx, const V *__restrict__ val, int64_t last_load,
+    const V *__restrict__ x, V alpha, V beta, V *__restrict__ y) {
+    constexpr int CH = kWave * ITEMS;
+    __shared__ double s_y[kSortedRowsMax];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x % kWave;
+    const uint32_t col_mask = (1u << col_bits) - 1;
+    for (int i = threadIdx.x; i < rows; i += kST) s_y[i] = 0.0;
+    __syncthreads();
+    const int64_t bs = blk_ptr[blockIdx.x], be = blk_ptr[blockIdx.x + 1];
+    // wave w streams slice w of the block (slices are multiples of 4 entries)
+    const int64_t per = ((be - bs + kSortedWaves - 1) / kSortedWaves + 3) & ~int64_t(3);
+    const int64_t start = std::min(be, bs + per * w), end = std::min(be, start + per);
+
+    using CI = Pack<int32_t, ITEMS>;
+    using CV = Pack<V, ITEMS>;
+    auto load = [&](int64_t q, CI &c, CV &v) {
+        const int64_t e = std::min<int64_t>(q + ITEMS * lane, last_load);
+        c = ld_i32<ITEMS>(idx + e);
+        v = ld_val<ITEMS>(val + e);
+    };
+    auto step = [&](int64_t q, const CI &c, const CV &v, CI &cn, CV &vn) {
+        V xv[ITEMS];
+        bool ok[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            ok[j] = (q + ITEMS * lane + j < end) && c.v[j] != kPanelPad;
+            xv[j] = x[ok[j] ? ((uint32_t)c.v[j] & col_mask) : 0u];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        load(q + CH, cn, vn);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j)
+            if (ok[j])
+                atomicAdd(&s_y[(uint32_t)c.v[j] >> col_bits], (double)v.v[j] * (double)xv[j]);
+    };
+    CI cA, cB;
+    CV vA, vB;
+    load(start, cA, vA);
+    for (int64_t q = start;;) {  // two steps per pass: the chunk buffers alternate
+        if (q >= end) break;
+        step(q, cA, vA, cB, vB);
+        q += CH;
+        if (q >= end) break;
+        step(q, cB, vB, cA, vA);
+        q += CH;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < rows; i += kST) {
+        const int64_t row = (int64_t)blockIdx.x * rows + i;
+        if (row < n_rows) store_y(y, row, s_y[i], alpha, beta);
+    }
+}
+
+__global__ void sorted_keys(const int32_t *__restrict__ row, const int32_t *__restrict__ col,
+                            int64_t nnz, int32_t rows, int32_t col_bits, uint64_t *__restrict__ key,
+                            uint32_t *__restrict__ perm) {
+    for (int64_t k = (int64_t)blockIdx.x * kB + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * kB) {
+        key[k] = ((uint64_t)(row[k] / rows) << col_bits) | (uint64_t)col[k];
+        perm[k] = (uint32_t)k;
+    }
+}
+
+template <class V>
+__global__ void sorted_scatter(const uint32_t *__restrict__ perm, int64_t nnz,
+                               const int32_t *__restrict__ row, const int32_t *__restrict__ col,
+                               const V *__restrict__ val, const int32_t *__restrict__ first,
+                               const int32_t *__restrict__ start, int32_t rows, int32_t col_bits,
+                               int32_t *__restrict__ idx_out, V *__restrict__ val_out) {
+    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * kB) {
+        const uint32_t e = perm[i];
+        const int32_t r = row[e];
+        const int64_t b = r / rows;
+        const int64_t pos = (int64_t)start[b] + (i - first[b]);
+        idx_out[pos] = (int32_t)(((uint32_t)(r % rows) << col_bits) | (uint32_t)col[e]);
+        val_out[pos] = val[e];
+    }
+}
+
+template <class V, int ITEMS>
+void launch_sorted(const spmv_matrix_s *h, double alpha, const void *x, double beta, void *y,
+                   hipStream_t s) {
+    const SortedPart &P = h->sorted;
+    const int64_t cap = padded_count(P.stream);
+    coo_sorted_kernel<V, ITEMS><<<P.blocks, kST, 0, s>>>(
+        h->n_rows, P.rows, P.col_bits, P.blk_ptr.as<int32_t>(), P.idx.as<int32_t>(), P.val.as<V>(),
+        cap - ITEMS, (const V *)x, (V)alpha, (V)beta, (V *)y);
+    SPMV_CHECK_LAUNCH();
+}
+
 }  // namespace
+
+void build_sorted(spmv_matrix_s *h, hipStream_t s) {
+    if (h->sorted.built) return;
+    const int64_t n = h->n_rows, nnz = h->nnz;
+    int col_bits = 1;
+    while ((int64_t(1) << col_bits) <= h->n_cols) ++col_bits;  // n_cols < 2^col_bits
+    const int row_bits = 32 - col_bits;
+    if (row_bits < 1 || nnz > (int64_t)INT32_MAX / 2)
+        fail(SPMV_ERR_NOT_APPLICABLE, "sorted-block COO cannot pack %d columns", h->n_cols);
+    int cus = 0;
+    SPMV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
+    SortedPart P;
+    P.col_bits = col_bits;
+    P.rows = (int32_t)std::min<int64_t>(
+        std::min<int64_t>(kSortedRowsMax, int64_t(1) << std::min(row_bits, 30)),
+        std::max<int64_t>(1, ceil_div(n, std::max(cus, 1))));
+    P.blocks = (int32_t)ceil_div(n, P.rows);
+    const int64_t blocks = P.blocks;
+    const size_t vs = dtype_size(h->dt);
+
+    DevBuf keys, perm, first, start;
+    first.alloc((blocks + 1) * 4);
+    start.alloc((blocks + 1) * 4);
+    panel_groups<<<grid_of_n(blocks + 1), kB, 0, s>>>(h->row_ptr.as<int32_t>(), h->n_rows, blocks,
+                                                      P.rows, first.as<int32_t>(),
+                                                      start.as<int32_t>());
+    SPMV_CHECK_LAUNCH();
+    exclusive_scan_i32(start.as<int32_t>(), start.as<int32_t>(), blocks + 1, s);
+    int32_t total = 0;
+    SPMV_HIP(hipMemcpyAsync(&total, start.as<int32_t>() + blocks, 4, hipMemcpyDeviceToHost, s));
+    SPMV_HIP(hipStreamSynchronize(s));
+    P.stream = total;
+    const int64_t cap = padded_count(total);
+    P.idx.alloc(cap * 4);
+    P.val.alloc(cap * vs);
+    SPMV_HIP(hipMemsetAsync(P.idx.p, 0xFF, cap * 4, s));  // kPanelPad
+    SPMV_HIP(hipMemsetAsync(P.val.p, 0, cap * vs, s));
+    if (nnz > 0) {
+        keys.alloc(nnz * 8);
+        perm.alloc(nnz * 4);
+        sorted_keys<<<grid_of_n(nnz), kB, 0, s>>>(h->row.as<int32_t>(), h->col.as<int32_t>(), nnz,
+                                                  P.rows, col_bits, keys.as<uint64_t>(),
+                                                  perm.as<uint32_t>());
+        SPMV_CHECK_LAUNCH();
+        int bits = col_bits;
+        while (bits < 64 && (uint64_t)(blocks - 1) >> (bits - col_bits)) ++bits;
+        radix_sort_pairs(keys, perm, nnz, bits, s);
+        if (h->dt == SPMV_F64)
+            sorted_scatter<double><<<grid_of_n(nnz), kB, 0, s>>>(
+                perm.as<uint32_t>(), nnz, h->row.as<int32_t>(), h->col.as<int32_t>(),
+                h->val.as<double>(), first.as<int32_t>(), start.as<int32_t>(), P.rows, col_bits,
+                P.idx.as<int32_t>(), P.val.as<double>());
+        else
+            sorted_scatter<float><<<grid_of_n(nnz), kB, 0, s>>>(
+                perm.as<uint32_t>(), nnz, h->row.as<int32_t>(), h->col.as<int32_t>(),
+                h->val.as<float>(), first.as<int32_t>(), start.as<int32_t>(), P.rows, col_bits,
+                P.idx.as<int32_t>(), P.val.as<float>());
+        SPMV_CHECK_LAUNCH();
+    }
+    P.blk_ptr = std::move(start);
+    SPMV_HIP(hipStreamSynchronize(s));
+    P.built = true;
+    h->sorted = std::move(P);
+}
+
+void sorted_spmv(const spmv_matrix_s *h, int items, double alpha, const void *x, double beta,
+                 void *y, hipStream_t s) {
+    if (!h->sorted.built) fail(SPMV_ERR_NOT_CONVERTED, "sorted-block COO layout not built");
+    if (h->n_rows == 0) return;
+    if (h->dt == SPMV_F64) {
+        if (items == 4) launch_sorted<double, 4>(h, alpha, x, beta, y, s);
+        else launch_sorted<double, 8>(h, alpha, x, beta, y, s);
+    } else {
+        if (items == 4) launch_sorted<float, 4>(h, alpha, x, beta, y, s);
+        else launch_sorted<float, 8>(h, alpha, x, beta, y, s);
+    }
+}
 
 void build_panel(spmv_matrix_s *h, hipStream_t s) {
     if (h->panel.built) return;

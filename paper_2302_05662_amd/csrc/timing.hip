@@ -112,10 +112,11 @@ double tune_format(spmv_matrix_s *h, spmv_format f, const void *x, void *y, int3
         if (m < best) { best = m; bi = v; }
     }
     h->variant[f] = bi;
-    // the panel copy of the entries is kept only while a panel variant is in use
-    if (h->panel.built && !variant_needs_panel(f, bi) && !variant_needs_panel(SPMV_FMT_COO, h->variant[SPMV_FMT_COO])) {
+    // the reordered copies of the COO entries are kept only while a variant uses them
+    if (f == SPMV_FMT_COO) {
         SPMV_HIP(hipStreamSynchronize(s));
-        h->panel = PanelPart{};
+        if (h->panel.built && !variant_needs_panel(f, bi)) h->panel = PanelPart{};
+        if (h->sorted.built && !variant_needs_sorted(f, bi)) h->sorted = SortedPart{};
     }
     if (best_idx) *best_idx = bi;
     return best;
