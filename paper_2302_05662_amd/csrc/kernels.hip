@@ -578,6 +578,19 @@ void csr_vector4_launch(const Args &a) {
     SPMV_CHECK_LAUNCH();
 }
 
+// The same kernel at another workgroup size (the thread-block size the paper
+// tunes in its compile-time mode).
+template <class V, int BLOCK, int L, int UNROLL>
+void csr_vector4_block_launch(const Args &a) {
+    const spmv_matrix_s *h = a.h;
+    if (h->n_rows == 0) return;
+    static_assert(BLOCK % L == 0 && BLOCK >= kWave, "a workgroup holds whole lane groups");
+    csr_vector4_kernel<V, BLOCK, L, UNROLL><<<grid_of(h->n_rows, BLOCK / L), BLOCK, 0, a.s>>>(
+        h->n_rows, h->row_ptr.as<int32_t>(), h->col.as<int32_t>(), h->val.as<V>(),
+        (const V *)a.x, (V)a.alpha, (V)a.beta, (V *)a.y);
+    SPMV_CHECK_LAUNCH();
+}
+
 template <class V, int L, int PASSES>
 void csr_pipe_launch(const Args &a) {
     const spmv_matrix_s *h = a.h;
@@ -693,6 +706,11 @@ CSRP(16, 2) CSRP(16, 4)
 CSRP(32, 2) CSRP(32, 4)
 CSRP(64, 2) CSRP(64, 4)
 #undef CSRP
+#define CSRB(B, L, U) \
+    template <class V> void csr_b##B##_##L##_##U(const Args &a) { csr_vector4_block_launch<V, B, L, U>(a); }
+CSRB(64, 4, 2) CSRB(128, 4, 2) CSRB(512, 4, 2) CSRB(1024, 4, 2)
+CSRB(64, 16, 2) CSRB(128, 16, 2) CSRB(512, 16, 2) CSRB(1024, 16, 2)
+#undef CSRB
 template <class V> void ell_p1(const Args &a) { ell_pipe_launch<V, 1, 1>(a); }
 template <class V> void ell_p2(const Args &a) { ell_pipe_launch<V, 2, 1>(a); }
 template <class V> void ell_p4(const Args &a) { ell_pipe_launch<V, 4, 1>(a); }
@@ -766,6 +784,14 @@ const std::vector<Variant> &table(spmv_format f) {
         VP(SPMV_KERNEL_CSR_VECTOR, 256, 32, 4, 4, csr_p32_4),
         VP(SPMV_KERNEL_CSR_VECTOR, 256, 64, 4, 2, csr_p64_2),
         VP(SPMV_KERNEL_CSR_VECTOR, 256, 64, 4, 4, csr_p64_4),
+        V4(SPMV_KERNEL_CSR_VECTOR, 64, 4, 2, csr_b64_4_2),
+        V4(SPMV_KERNEL_CSR_VECTOR, 128, 4, 2, csr_b128_4_2),
+        V4(SPMV_KERNEL_CSR_VECTOR, 512, 4, 2, csr_b512_4_2),
+        V4(SPMV_KERNEL_CSR_VECTOR, 1024, 4, 2, csr_b1024_4_2),
+        V4(SPMV_KERNEL_CSR_VECTOR, 64, 16, 2, csr_b64_16_2),
+        V4(SPMV_KERNEL_CSR_VECTOR, 128, 16, 2, csr_b128_16_2),
+        V4(SPMV_KERNEL_CSR_VECTOR, 512, 16, 2, csr_b512_16_2),
+        V4(SPMV_KERNEL_CSR_VECTOR, 1024, 16, 2, csr_b1024_16_2),
     };
     static const std::vector<Variant> coo = {
         VN(SPMV_KERNEL_COO, 256, 2, 1, 2, coo_2),

@@ -310,9 +310,13 @@ void build_sorted(spmv_matrix_s *h, hipStream_t s) {
     SPMV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
     SortedPart P;
     P.col_bits = col_bits;
+    // as few blocks as possible (more entries per line of x in a block), in whole
+    // rounds of one block per CU
+    const int64_t ncu = std::max(cus, 1);
+    const int64_t rounds = std::max<int64_t>(1, ceil_div(n, ncu * kSortedRowsMax));
     P.rows = (int32_t)std::min<int64_t>(
         std::min<int64_t>(kSortedRowsMax, int64_t(1) << std::min(row_bits, 30)),
-        std::max<int64_t>(1, ceil_div(n, std::max(cus, 1))));
+        std::max<int64_t>(1, ceil_div(n, ncu * rounds)));
     P.blocks = (int32_t)ceil_div(n, P.rows);
     const int64_t blocks = P.blocks;
     const size_t vs = dtype_size(h->dt);

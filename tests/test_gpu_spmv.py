@@ -185,3 +185,40 @@ def test_panel_variants_with_unaligned_x(dtype):
         ga, gu = ya.cpu().numpy(), yu.cpu().numpy()
         assert ga.tobytes() == gu.tobytes(), var
         assert OS.max_row_error(ga, y_ref, den) <= C.TOL[dtype]
+
+
+def test_reordered_coo_layouts_at_their_column_limits():
+    """Streaming COO packs columns in 23 bits and refuses wider matrices; sorted-block COO
+    packs the row in the bits the column leaves free and still runs."""
+    n_rows, n_cols = 3000, (1 << 23) + 5
+    rng = np.random.default_rng(21)
+    rows = np.repeat(np.arange(n_rows), 3)
+    cols = np.concatenate([np.sort(rng.choice(n_cols, 3, replace=False)) for _ in range(n_rows)])
+    cols[-1] = n_cols - 1  # the last column is used
+    m = synth.from_coords("wide_cols", n_rows, n_cols, rows, cols, 22)
+    print(f"[spmv wide cols] n_cols={n_cols}", flush=True)
+    v = m.values(np.float32)
+    h = S.spmv_create(m.n_rows, m.n_cols, m.row, m.col, v)
+    kinds = {i: S.spmv_variant_describe(S.SPMV_FMT_COO, S.SPMV_F32, i)["kernel"]
+             for i in range(S.spmv_variant_count(S.SPMV_FMT_COO, S.SPMV_F32))}
+    x = synth.uniform_vector(n_cols, np.float32, [22, 3])
+    xd = torch.from_numpy(x).cuda()
+    row_ptr = np.zeros(n_rows + 1, np.int64)
+    np.cumsum(np.bincount(m.row, minlength=n_rows), out=row_ptr[1:])
+    c = OF.canonicalize(n_rows, n_cols, m.row, m.col, v)
+    y_ref = OS.spmv_csr(c["row_ptr"], c["col"], c["val"], x, np.float32(1.0), np.float32(0.0), None)
+    den = OS.row_denominator(c["row_ptr"], c["col"], c["val"], x, np.float32(1.0), np.float32(0.0), None)
+    for i, k in kinds.items():
+        if k == "coo_panel":
+            with pytest.raises(S.SpmvError) as e:
+                S.spmv_set_variant(h, S.SPMV_FMT_COO, i)
+            assert e.value.status == "NOT_APPLICABLE"
+        elif k == "coo_sorted":
+            S.spmv_set_variant(h, S.SPMV_FMT_COO, i)
+            yd = torch.zeros(n_rows, dtype=torch.float32, device="cuda")
+            S.spmv_run(h, S.SPMV_FMT_COO, 1.0, xd, 0.0, yd)
+            assert OS.max_row_error(yd.cpu().numpy(), y_ref, den) <= C.TOL[np.float32]
+    # tuning skips the variants that do not apply and keeps a runnable one
+    yd = torch.zeros(n_rows, dtype=torch.float32, device="cuda")
+    var, _ = S.spmv_tune(h, S.SPMV_FMT_COO, xd, yd, reps=2, flush=False)
+    assert kinds[var] != "coo_panel"
