@@ -241,7 +241,13 @@ typedef struct spmv_batch_config {
                                 bit-equal to the single CSR vector launch with those
                                 lanes and unroll); 1: per tile (lanes from the tile's
                                 longest row; rows of >= 2048 entries get a tile of
-                                their own reduced by the whole workgroup)            */
+                                their own reduced by the whole workgroup); 2: the
+                                batch's sorted-block COO copy of every matrix, one
+                                block (<= 4096 rows, entries sorted by column) per
+                                1024-thread tile, largest first, unroll 1/2 = 4/8
+                                entries per lane; the order of the FP64 row sums is
+                                not fixed (see SPMV_KERNEL_COO_SORTED); needs a
+                                second copy of every matrix's entries               */
     int32_t total_tiles;     /* row tiles over the whole batch                       */
     int32_t grid;            /* workgroups launched                                  */
     float tuned_ms;          /* median graph time of the chosen setting (0: untuned) */
@@ -275,7 +281,8 @@ spmv_status spmv_batch_get_config(spmv_batch b, spmv_batch_config *out, int32_t 
 
 /* Rebuild the batch's graph with the setting *cfg (block, total_tiles, grid and
  * tuned_ms are ignored): unroll 1 or 2, passes_per_tile >= 1, blocks_per_cu
- * >= 1, lanes_divisor >= 1, tiling 0 or 1. Errors: INVALID_ARG, HIP.
+ * >= 1, lanes_divisor >= 1, tiling 0, 1 or 2. Errors: INVALID_ARG, NOT_APPLICABLE
+ * (tiling 2 on a matrix whose columns leave no bits for rows), OOM, HIP.
  * Synchronises `stream`. */
 spmv_status spmv_batch_set_config(spmv_batch b, const spmv_batch_config *cfg, void *stream);
 

@@ -18,7 +18,10 @@
 // kernel, so y is bit-equal to a single launch with the same lanes and unroll),
 // and per tile (a tile takes the lanes of its longest row, and a row of 2048 or
 // more entries gets a tile of its own reduced by the whole workgroup), which
-// keeps power-law rows from setting the tail.
+// keeps power-law rows from setting the tail. A third tiling uses the batch's
+// own sorted-block COO copy of every matrix (blocks of up to 4096 rows, entries
+// sorted by column): a tile is one block, taken by a 1024-thread workgroup, and
+// tiles are handed out largest first.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -33,6 +36,7 @@ constexpr int kBlock = 256;
 constexpr int kMaxBatch = 8192;
 constexpr int kBlockRow = 8;          // lanes_log2 value meaning "the whole workgroup"
 constexpr int32_t kLongRow = 2048;    // entries from which a row gets its own tile
+constexpr int kSortedBlock = kSortedWaves * kWave;  // workgroup size of the sorted tiling
 
 struct BatchDesc {
     const int32_t *rp;
@@ -43,6 +47,12 @@ struct BatchDesc {
     int32_t n_rows;
     int32_t pad;
     double alpha, beta;
+    // sorted-block copy (tiling 2)
+    const int32_t *sblk;
+    const int32_t *sidx;
+    const void *sval;
+    int64_t slast;  // last 16-byte-aligned load position of the copy
+    int32_t srows, scol_bits;
 };
 
 struct BatchTile {
@@ -118,9 +128,41 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchDesc *__restri
     }
 }
 
+// Tiling 2: tile = one sorted block (matrix, block index in row_begin).
+template <class V, int ITEMS>
+__global__ __launch_bounds__(kSortedBlock) void batch_sorted_kernel(
+    const BatchDesc *__restrict__ desc, const BatchTile *__restrict__ tiles, int32_t n_tiles,
+    int32_t *__restrict__ counter) {
+    __shared__ double s_y[kSortedRowsMax];
+    __shared__ int32_t s_tile;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
+        __syncthreads();
+        const int32_t t = s_tile;
+        __syncthreads();  // every thread has read s_tile before thread 0 takes the next tile
+        if (t >= n_tiles) break;
+        const BatchTile tl = tiles[t];
+        const BatchDesc d = desc[tl.matrix];
+        const int64_t row0 = (int64_t)tl.row_begin * d.srows;
+        const int nr = (int)std::min<int64_t>(d.srows, d.n_rows - row0);
+        for (int i = threadIdx.x; i < nr; i += kSortedBlock) s_y[i] = 0.0;
+        __syncthreads();
+        sorted_block_sum<V, ITEMS, kSortedWaves>(d.sidx, (const V *)d.sval, (const V *)d.x,
+                                                 d.sblk[tl.row_begin], d.sblk[tl.row_begin + 1],
+                                                 d.scol_bits, d.slast, s_y);
+        __syncthreads();
+        for (int i = threadIdx.x; i < nr; i += kSortedBlock)
+            store_y((V *)d.y, row0 + i, s_y[i], (V)d.alpha, (V)d.beta);
+    }
+}
+
 using BatchKernel = void (*)(const BatchDesc *, const BatchTile *, int32_t, int32_t *);
 
-BatchKernel kernel_for(spmv_dtype dt, int unroll) {
+BatchKernel kernel_for(spmv_dtype dt, int unroll, int tiling) {
+    if (tiling == 2) {
+        if (dt == SPMV_F64) return unroll == 2 ? batch_sorted_kernel<double, 8> : batch_sorted_kernel<double, 4>;
+        return unroll == 2 ? batch_sorted_kernel<float, 8> : batch_sorted_kernel<float, 4>;
+    }
     if (dt == SPMV_F64) return unroll == 2 ? batch_kernel<double, 2> : batch_kernel<double, 1>;
     return unroll == 2 ? batch_kernel<float, 2> : batch_kernel<float, 1>;
 }
@@ -143,6 +185,7 @@ struct spmv_batch_s {
     std::vector<std::vector<int32_t>> row_ptr;  // host copies, for tiling
     std::vector<spmv::BatchDesc> desc;
     std::vector<int32_t> lanes;  // per matrix, for the per-matrix tiling
+    std::vector<spmv::SortedPart> sorted;  // per matrix, built on first use of tiling 2
     spmv::DevBuf d_desc, d_tiles, d_counter;
     spmv_batch_config cfg{};
     int num_cu = 0;
@@ -163,6 +206,21 @@ namespace {
 std::vector<BatchTile> plan_tiles(spmv_batch_s *b, const spmv_batch_config &c) {
     std::vector<BatchTile> tiles;
     b->lanes.assign(b->hs.size(), 0);
+    if (c.tiling == 2) {  // one tile per sorted block, largest first
+        std::vector<std::pair<int32_t, BatchTile>> sized;
+        for (size_t m = 0; m < b->hs.size(); ++m) {
+            const std::vector<int32_t> &rp = b->row_ptr[m];
+            const int32_t n = b->hs[m]->n_rows, rows = b->sorted[m].rows;
+            for (int32_t k = 0; k < b->sorted[m].blocks; ++k) {
+                const int32_t r0 = k * rows, r1 = std::min(n, r0 + rows);
+                sized.push_back({rp[r1] - rp[r0], BatchTile{(int32_t)m, k, r1, 0}});
+            }
+        }
+        std::stable_sort(sized.begin(), sized.end(),
+                         [](const auto &a, const auto &z) { return a.first > z.first; });
+        for (const auto &e : sized) tiles.push_back(e.second);
+        return tiles;
+    }
     for (size_t m = 0; m < b->hs.size(); ++m) {
         const spmv_matrix_s *h = b->hs[m];
         const std::vector<int32_t> &rp = b->row_ptr[m];
@@ -202,12 +260,31 @@ void upload_desc(spmv_batch_s *b, hipStream_t s) {
 }
 
 // (Re)build the graph {reset counter, persistent kernel} for configuration c.
+void ensure_sorted(spmv_batch_s *b, hipStream_t s) {
+    if (!b->sorted.empty()) return;
+    std::vector<SortedPart> parts(b->hs.size());
+    for (size_t m = 0; m < b->hs.size(); ++m)
+        build_sorted_into(b->hs[m], sorted_max_rows(b->hs[m]), parts[m], s);
+    b->sorted = std::move(parts);
+    for (size_t m = 0; m < b->hs.size(); ++m) {
+        const SortedPart &P = b->sorted[m];
+        BatchDesc &d = b->desc[m];
+        d.sblk = P.blk_ptr.as<int32_t>();
+        d.sidx = P.idx.as<int32_t>();
+        d.sval = P.val.p;
+        d.slast = padded_count(P.stream) - 8;  // covers 4 and 8 entries per lane
+        d.srows = P.rows;
+        d.scol_bits = P.col_bits;
+    }
+}
+
 void build_graph(spmv_batch_s *b, const spmv_batch_config &c, hipStream_t user) {
     spmv_batch_config cc = c;
+    if (cc.tiling == 2) ensure_sorted(b, user);
     const std::vector<BatchTile> tiles = plan_tiles(b, cc);
     cc.total_tiles = (int32_t)tiles.size();
     cc.grid = std::max(1, std::min(cc.total_tiles, b->num_cu * cc.blocks_per_cu));
-    cc.block = kBlock;
+    cc.block = cc.tiling == 2 ? kSortedBlock : kBlock;
     SPMV_HIP(hipStreamSynchronize(user));  // no earlier run may still read the old tiles
     b->d_tiles.alloc(std::max<size_t>(tiles.size(), 1) * sizeof(BatchTile));
     if (!tiles.empty())
@@ -221,8 +298,8 @@ void build_graph(spmv_batch_s *b, const spmv_batch_config &c, hipStream_t user) 
     SPMV_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     reset_counter<<<1, 1, 0, cs>>>(b->d_counter.as<int32_t>());
     if (cc.total_tiles > 0) {
-        BatchKernel k = kernel_for(b->dt, cc.unroll);
-        k<<<cc.grid, kBlock, 0, cs>>>(b->d_desc.as<BatchDesc>(), b->d_tiles.as<BatchTile>(),
+        BatchKernel k = kernel_for(b->dt, cc.unroll, cc.tiling);
+        k<<<cc.grid, cc.block, 0, cs>>>(b->d_desc.as<BatchDesc>(), b->d_tiles.as<BatchTile>(),
                                       cc.total_tiles, b->d_counter.as<int32_t>());
     }
     hipError_t launch_err = hipGetLastError();
@@ -356,6 +433,7 @@ extern "C" spmv_status spmv_batch_create(spmv_batch *out, const spmv_handle *hs,
         }
         double best = INFINITY;
         spmv_batch_config bc = dflt;
+        std::vector<spmv_batch_config> grid_cfgs;
         for (int tiling : {0, 1})
             for (int unroll : {1, 2})
                 for (int passes : {1, 4, 16})
@@ -367,10 +445,34 @@ extern "C" spmv_status spmv_batch_create(spmv_batch *out, const spmv_handle *hs,
                             c.passes_per_tile = passes;
                             c.blocks_per_cu = bpc;
                             c.lanes_divisor = div;
-                            build_graph(b, c, s);
-                            const double t = time_graph(b, 5, s);
-                            if (t < best) { best = t; bc = b->cfg; }
+                            grid_cfgs.push_back(c);
                         }
+        bool sorted_ok = true;
+        for (int32_t i = 0; i < count; ++i) {
+            try {
+                (void)sorted_max_rows(hs[i]);
+            } catch (const Error &e) {
+                if (e.status != SPMV_ERR_NOT_APPLICABLE) throw;
+                clear_error();
+                sorted_ok = false;
+            }
+        }
+        if (sorted_ok)
+            for (int unroll : {1, 2})
+                for (int bpc : {1, 2}) {
+                    spmv_batch_config c{};
+                    c.tiling = 2;
+                    c.unroll = unroll;
+                    c.passes_per_tile = 1;
+                    c.blocks_per_cu = bpc;
+                    c.lanes_divisor = 1;
+                    grid_cfgs.push_back(c);
+                }
+        for (const spmv_batch_config &gc : grid_cfgs) {
+            build_graph(b, gc, s);
+            const double t = time_graph(b, 5, s);
+            if (t < best) { best = t; bc = b->cfg; }
+        }
         SPMV_HIP(hipStreamSynchronize(s));
         for (int32_t i = 0; i < count; ++i) b->desc[i].y = real_y[i];
         build_graph(b, bc, s);
@@ -417,7 +519,7 @@ extern "C" spmv_status spmv_batch_set_config(spmv_batch b, const spmv_batch_conf
     return guard([&] {
         if (!b || !cfg) fail(SPMV_ERR_INVALID_ARG, "NULL argument");
         if ((cfg->unroll != 1 && cfg->unroll != 2) || cfg->passes_per_tile < 1 ||
-            cfg->blocks_per_cu < 1 || cfg->lanes_divisor < 1 || (cfg->tiling != 0 && cfg->tiling != 1))
+            cfg->blocks_per_cu < 1 || cfg->lanes_divisor < 1 || cfg->tiling < 0 || cfg->tiling > 2)
             fail(SPMV_ERR_INVALID_ARG, "bad batch setting");
         build_graph(b, *cfg, (hipStream_t)stream);
     });

@@ -188,6 +188,10 @@ void build_panel(spmv_matrix_s *h, hipStream_t s);  // NOT_APPLICABLE past the i
 void panel_spmv(const spmv_matrix_s *h, int items, double alpha, const void *x, double beta,
                 void *y, hipStream_t s);
 void build_sorted(spmv_matrix_s *h, hipStream_t s);
+// Tallest sorted block the packing allows for this matrix (NOT_APPLICABLE if none).
+int32_t sorted_max_rows(const spmv_matrix_s *h);
+// Build a sorted-block copy with blocks of `rows` rows into P (used by the batch).
+void build_sorted_into(const spmv_matrix_s *h, int32_t rows, SortedPart &P, hipStream_t s);
 void sorted_spmv(const spmv_matrix_s *h, int items, double alpha, const void *x, double beta,
                  void *y, hipStream_t s);
 

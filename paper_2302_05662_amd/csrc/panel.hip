@@ -207,57 +207,15 @@ __global__ __launch_bounds__(kST) void coo_sorted_kernel(
     int32_t n_rows, int32_t rows, int32_t col_bits, const int32_t *__restrict__ blk_ptr,
     const int32_t *__restrict__ idx, const V *__restrict__ val, int64_t last_load,
     const V *__restrict__ x, V alpha, V beta, V *__restrict__ y) {
-    constexpr int CH = kWave * ITEMS;
     __shared__ double s_y[kSortedRowsMax];
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int lane = threadIdx.x % kWave;
-    const uint32_t col_mask = (1u << col_bits) - 1;
-    for (int i = threadIdx.x; i < rows; i += kST) s_y[i] = 0.0;
+    const int64_t row0 = (int64_t)blockIdx.x * rows;
+    const int nr = (int)std::min<int64_t>(rows, n_rows - row0);
+    for (int i = threadIdx.x; i < nr; i += kST) s_y[i] = 0.0;
     __syncthreads();
-    const int64_t bs = blk_ptr[blockIdx.x], be = blk_ptr[blockIdx.x + 1];
-    // wave w streams slice w of the block (slices are multiples of 4 entries)
-    const int64_t per = ((be - bs + kSortedWaves - 1) / kSortedWaves + 3) & ~int64_t(3);
-    const int64_t start = std::min(be, bs + per * w), end = std::min(be, start + per);
-
-    using CI = Pack<int32_t, ITEMS>;
-    using CV = Pack<V, ITEMS>;
-    auto load = [&](int64_t q, CI &c, CV &v) {
-        const int64_t e = std::min<int64_t>(q + ITEMS * lane, last_load);
-        c = ld_i32<ITEMS>(idx + e);
-        v = ld_val<ITEMS>(val + e);
-    };
-    auto step = [&](int64_t q, const CI &c, const CV &v, CI &cn, CV &vn) {
-        V xv[ITEMS];
-        bool ok[ITEMS];
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            ok[j] = (q + ITEMS * lane + j < end) && c.v[j] != kPanelPad;
-            xv[j] = x[ok[j] ? ((uint32_t)c.v[j] & col_mask) : 0u];
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        load(q + CH, cn, vn);
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j)
-            if (ok[j])
-                atomicAdd(&s_y[(uint32_t)c.v[j] >> col_bits], (double)v.v[j] * (double)xv[j]);
-    };
-    CI cA, cB;
-    CV vA, vB;
-    load(start, cA, vA);
-    for (int64_t q = start;;) {  // two steps per pass: the chunk buffers alternate
-        if (q >= end) break;
-        step(q, cA, vA, cB, vB);
-        q += CH;
-        if (q >= end) break;
-        step(q, cB, vB, cA, vA);
-        q += CH;
-    }
+    sorted_block_sum<V, ITEMS, kSortedWaves>(idx, val, x, blk_ptr[blockIdx.x],
+                                             blk_ptr[blockIdx.x + 1], col_bits, last_load, s_y);
     __syncthreads();
-    for (int i = threadIdx.x; i < rows; i += kST) {
-        const int64_t row = (int64_t)blockIdx.x * rows + i;
-        if (row < n_rows) store_y(y, row, s_y[i], alpha, beta);
-    }
+    for (int i = threadIdx.x; i < nr; i += kST) store_y(y, row0 + i, s_y[i], alpha, beta);
 }
 
 __global__ void sorted_keys(const int32_t *__restrict__ row, const int32_t *__restrict__ col,
@@ -298,25 +256,40 @@ void launch_sorted(const spmv_matrix_s *h, double alpha, const void *x, double b
 
 }  // namespace
 
-void build_sorted(spmv_matrix_s *h, hipStream_t s) {
-    if (h->sorted.built) return;
-    const int64_t n = h->n_rows, nnz = h->nnz;
+int32_t sorted_max_rows(const spmv_matrix_s *h) {
     int col_bits = 1;
     while ((int64_t(1) << col_bits) <= h->n_cols) ++col_bits;  // n_cols < 2^col_bits
     const int row_bits = 32 - col_bits;
-    if (row_bits < 1 || nnz > (int64_t)INT32_MAX / 2)
+    if (row_bits < 1 || h->nnz > (int64_t)INT32_MAX / 2)
         fail(SPMV_ERR_NOT_APPLICABLE, "sorted-block COO cannot pack %d columns", h->n_cols);
+    return (int32_t)std::min<int64_t>(kSortedRowsMax, int64_t(1) << std::min(row_bits, 30));
+}
+
+void build_sorted(spmv_matrix_s *h, hipStream_t s) {
+    if (h->sorted.built) return;
+    const int32_t max_rows = sorted_max_rows(h);
     int cus = 0;
     SPMV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
-    SortedPart P;
-    P.col_bits = col_bits;
     // as few blocks as possible (more entries per line of x in a block), in whole
     // rounds of one block per CU
-    const int64_t ncu = std::max(cus, 1);
+    const int64_t n = h->n_rows, ncu = std::max(cus, 1);
     const int64_t rounds = std::max<int64_t>(1, ceil_div(n, ncu * kSortedRowsMax));
-    P.rows = (int32_t)std::min<int64_t>(
-        std::min<int64_t>(kSortedRowsMax, int64_t(1) << std::min(row_bits, 30)),
-        std::max<int64_t>(1, ceil_div(n, ncu * rounds)));
+    const int32_t rows = (int32_t)std::min<int64_t>(
+        max_rows, std::max<int64_t>(1, ceil_div(n, ncu * rounds)));
+    SortedPart P;
+    build_sorted_into(h, rows, P, s);
+    h->sorted = std::move(P);
+}
+
+void build_sorted_into(const spmv_matrix_s *h, int32_t rows, SortedPart &P, hipStream_t s) {
+    const int32_t max_rows = sorted_max_rows(h);
+    if (rows < 1 || rows > max_rows) fail(SPMV_ERR_INVALID_ARG, "bad sorted block height %d", rows);
+    const int64_t n = h->n_rows, nnz = h->nnz;
+    int col_bits = 1;
+    while ((int64_t(1) << col_bits) <= h->n_cols) ++col_bits;
+    P = SortedPart{};
+    P.col_bits = col_bits;
+    P.rows = rows;
     P.blocks = (int32_t)ceil_div(n, P.rows);
     const int64_t blocks = P.blocks;
     const size_t vs = dtype_size(h->dt);
@@ -363,7 +336,6 @@ void build_sorted(spmv_matrix_s *h, hipStream_t s) {
     P.blk_ptr = std::move(start);
     SPMV_HIP(hipStreamSynchronize(s));
     P.built = true;
-    h->sorted = std::move(P);
 }
 
 void sorted_spmv(const spmv_matrix_s *h, int items, double alpha, const void *x, double beta,

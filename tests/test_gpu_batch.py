@@ -64,7 +64,8 @@ def test_batch_matches_oracle_and_single_launches(dtype, tune):
     b = S.spmv_batch_create(hs, xs, ys, alphas, betas, tune=tune)
     tol = 1e-5 if dtype == np.float32 else 1e-12
     settings = [None, dict(tiling=1, unroll=2, passes_per_tile=1, lanes_divisor=2),
-                dict(tiling=0, unroll=1), dict(tiling=0, unroll=2, passes_per_tile=16)]
+                dict(tiling=0, unroll=1), dict(tiling=0, unroll=2, passes_per_tile=16),
+                dict(tiling=2, unroll=1, blocks_per_cu=1), dict(tiling=2, unroll=2, blocks_per_cu=2)]
     for setting in settings:
         if setting is not None:
             S.spmv_batch_set_config(b, **setting)
@@ -88,11 +89,15 @@ def test_batch_matches_oracle_and_single_launches(dtype, tune):
             assert ys_single.cpu().numpy().tobytes() == got.tobytes(), (setting, m.name)
 
 
-def test_graph_replays_with_new_vectors_and_eager_work_between():
+@pytest.mark.parametrize("tiling", [1, 2])
+def test_graph_replays_with_new_vectors_and_eager_work_between(tiling):
     dtype = np.float32
     ms, hs, xs, ys, refs, y0s, alphas, betas = _setup(dtype, 31)
+    print(f"[batch replay] tiling {tiling}", flush=True)
     zero_b = [0.0] * len(ms)
     b = S.spmv_batch_create(hs, xs, ys, alphas, zero_b, tune=False)
+    if tiling == 2:
+        S.spmv_batch_set_config(b, tiling=2, unroll=2, blocks_per_cu=2)
     for rep in range(3):
         new_x = [torch.from_numpy(synth.uniform_vector(m.n_cols, dtype, [m.seed, 100 + rep])).cuda()
                  for m in ms]
