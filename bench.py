@@ -85,6 +85,8 @@ def kernel_symbols(fmt, info, dtype="float"):
         return [f"coo_panel_kernel<{dtype}, {l}>"]
     if info["kernel"] == "coo_sorted":
         return [f"coo_sorted_kernel<{dtype}, {l}>"]
+    if info["kernel"] == "coo_split":
+        return [f"coo_tile_kernel<{dtype}, {b}, {l}, false>", f"coo_tile_kernel<{dtype}, {b}, {l}, true>"]
     if info["kernel"] == "coo":
         return [f"coo_tile_kernel<{dtype}, {b}, {l}, false>", f"coo_fixup<{dtype}, {b * l}, false>"]
     if info["kernel"] == "ell":

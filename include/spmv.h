@@ -65,12 +65,16 @@ typedef enum spmv_kernel {
                                    gathers stay in a window of x; needs a second
                                    copy of the entries, built by spmv_set_variant
                                    / spmv_tune / spmv_time; n_cols < 2^23 - 1     */
-    SPMV_KERNEL_COO_SORTED = 6  /* COO entries of each block of rows sorted by
+    SPMV_KERNEL_COO_SORTED = 6, /* COO entries of each block of rows sorted by
                                    column, so a wave's gathers share cache lines;
                                    rows summed with LDS atomics across the block's
                                    16 waves: the order of the FP64 additions, and
                                    so the last bits of a result, may vary between
                                    runs; second copy of the entries as above      */
+    SPMV_KERNEL_COO_SPLIT = 7   /* tiled COO run once per 2 MB column panel of x
+                                   over a copy ordered by (panel, row, column), the
+                                   first pass writing y, the others adding; only
+                                   for matrices with more than one panel          */
 } spmv_kernel;
 
 typedef enum spmv_select_mode {

@@ -131,10 +131,12 @@ spmv_format select_rule(const float f[12], float votes[4]) {
 bool prepare_variant(spmv_matrix_s *h, spmv_format f, int32_t idx, hipStream_t s) {
     const bool panel = variant_needs_panel(f, idx) && !h->panel.built;
     const bool sorted = variant_needs_sorted(f, idx) && !h->sorted.built;
-    if (!panel && !sorted) return true;
+    const bool split = variant_needs_split(f, idx) && !h->split.built;
+    if (!panel && !sorted && !split) return true;
     try {
         if (panel) build_panel(h, s);
         if (sorted) build_sorted(h, s);
+        if (split) build_split(h, s);
     } catch (const Error &e) {
         if (e.status != SPMV_ERR_NOT_APPLICABLE) throw;
         clear_error();

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <vector>
 
 #include <cstdint>
 #include <cstdio>
@@ -143,6 +144,17 @@ struct SortedPart {
     DevBuf idx, val, blk_ptr;
 };
 
+// Column-split copy of the COO entries: entries ordered by column panel (2 MB
+// of x per panel), then row, then column; panel p's entries start at start[p]
+// (a multiple of 4) and number count[p]. Three arrays like canonical COO.
+struct SplitPart {
+    bool built = false;
+    int32_t panels = 0, width = 0;
+    std::vector<int64_t> start, count;
+    DevBuf row, col, val;
+};
+inline int32_t split_width(spmv_dtype dt) { return dt == SPMV_F64 ? (1 << 18) : (1 << 19); }
+
 // Row-length statistics kept from ingest (used by defaults and features).
 struct RowStats {
     int32_t max_len = 0;
@@ -163,6 +175,7 @@ struct spmv_matrix_s {
     spmv::HybPart hyb;
     spmv::PanelPart panel;    // built on first use of a streaming COO variant
     spmv::SortedPart sorted;  // built on first use of a sorted-block COO variant
+    spmv::SplitPart split;    // built on first use of a column-split COO variant
     spmv::RowStats stats;
     int32_t variant[SPMV_NUM_FORMATS] = {0, 0, 0, 0};
 };
@@ -192,6 +205,7 @@ void build_sorted(spmv_matrix_s *h, hipStream_t s);
 int32_t sorted_max_rows(const spmv_matrix_s *h);
 // Build a sorted-block copy with blocks of `rows` rows into P (used by the batch).
 void build_sorted_into(const spmv_matrix_s *h, int32_t rows, SortedPart &P, hipStream_t s);
+void build_split(spmv_matrix_s *h, hipStream_t s);  // NOT_APPLICABLE below two panels
 void sorted_spmv(const spmv_matrix_s *h, int items, double alpha, const void *x, double beta,
                  void *y, hipStream_t s);
 
@@ -201,6 +215,7 @@ bool variant_describe(spmv_format f, spmv_dtype dt, int32_t idx, spmv_variant_in
 int32_t default_variant(const spmv_matrix_s *h, spmv_format f);
 bool variant_needs_panel(spmv_format f, int32_t idx);
 bool variant_needs_sorted(spmv_format f, int32_t idx);
+bool variant_needs_split(spmv_format f, int32_t idx);
 // Make variant idx of f runnable: builds the panel layout for a panel variant.
 // Returns false when that layout is not applicable to the matrix.
 bool prepare_variant(spmv_matrix_s *h, spmv_format f, int32_t idx, hipStream_t s);

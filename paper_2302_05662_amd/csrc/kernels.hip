@@ -503,6 +503,27 @@ inline int grid_of(int64_t units, int per_block) {
     return (int)g;
 }
 
+// Column-split COO: one tiled COO pass per column panel of the split copy; the
+// first pass writes every y_i (alpha*s + beta*y), the others add alpha*s.
+template <class V, int ITEMS>
+void coo_split_launch(const Args &a) {
+    const spmv_matrix_s *h = a.h;
+    const SplitPart &P = h->split;
+    if (!P.built) fail(SPMV_ERR_NOT_CONVERTED, "column-split COO copy not built");
+    if (h->n_rows == 0) return;
+    for (int32_t p = 0; p < P.panels; ++p) {
+        const int64_t off = P.start[p];
+        const int32_t *row = P.row.as<int32_t>() + off, *col = P.col.as<int32_t>() + off;
+        const V *val = P.val.as<V>() + off;
+        if (p == 0)
+            coo_launch_impl<V, ITEMS, false>(P.count[p], h->n_rows, row, col, val, a,
+                                             h->coo_partials.as<double>());
+        else
+            coo_launch_impl<V, ITEMS, true>(P.count[p], h->n_rows, row, col, val, a,
+                                            h->coo_partials.as<double>());
+    }
+}
+
 template <class V>
 void launch_coo_arrays(int64_t nnz, int32_t n_rows, const int32_t *row, const int32_t *col,
                        const V *val, const Args &a, double *part, int items, bool accum);
@@ -727,6 +748,8 @@ template <class V> void coo_panel_4(const Args &a) { panel_spmv(a.h, 4, a.alpha,
 template <class V> void coo_panel_8(const Args &a) { panel_spmv(a.h, 8, a.alpha, a.x, a.beta, a.y, a.s); }
 template <class V> void coo_sorted_4(const Args &a) { sorted_spmv(a.h, 4, a.alpha, a.x, a.beta, a.y, a.s); }
 template <class V> void coo_sorted_8(const Args &a) { sorted_spmv(a.h, 8, a.alpha, a.x, a.beta, a.y, a.s); }
+template <class V> void coo_split_4(const Args &a) { coo_split_launch<V, 4>(a); }
+template <class V> void coo_split_8(const Args &a) { coo_split_launch<V, 8>(a); }
 template <class V> void ell_1_1(const Args &a) { ell_launch<V, 1, 1>(a); }
 template <class V> void ell_1_2(const Args &a) { ell_launch<V, 1, 2>(a); }
 template <class V> void ell_2_1(const Args &a) { ell_launch<V, 2, 1>(a); }
@@ -801,6 +824,8 @@ const std::vector<Variant> &table(spmv_format f) {
         VP(SPMV_KERNEL_COO_PANEL, 512, 8, 4, 1, coo_panel_8),
         VP(SPMV_KERNEL_COO_SORTED, 1024, 4, 4, 1, coo_sorted_4),
         VP(SPMV_KERNEL_COO_SORTED, 1024, 8, 4, 1, coo_sorted_8),
+        VN(SPMV_KERNEL_COO_SPLIT, 256, 4, 1, 4, coo_split_4),
+        VN(SPMV_KERNEL_COO_SPLIT, 256, 8, 1, 4, coo_split_8),
     };
     static const std::vector<Variant> ell = {
         VN(SPMV_KERNEL_ELL, 256, 1, 1, 1, ell_1_1), VN(SPMV_KERNEL_ELL, 256, 1, 2, 1, ell_1_2),
@@ -870,6 +895,11 @@ int32_t default_variant(const spmv_matrix_s *h, spmv_format f) {
 bool variant_needs_panel(spmv_format f, int32_t idx) {
     const auto &t = table(f);
     return idx >= 0 && idx < (int32_t)t.size() && t[idx].info.kernel == SPMV_KERNEL_COO_PANEL;
+}
+
+bool variant_needs_split(spmv_format f, int32_t idx) {
+    const auto &t = table(f);
+    return idx >= 0 && idx < (int32_t)t.size() && t[idx].info.kernel == SPMV_KERNEL_COO_SPLIT;
 }
 
 bool variant_needs_sorted(spmv_format f, int32_t idx) {

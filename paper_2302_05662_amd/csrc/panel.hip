@@ -254,7 +254,110 @@ void launch_sorted(const spmv_matrix_s *h, double alpha, const void *x, double b
     SPMV_CHECK_LAUNCH();
 }
 
+// ---- column-split COO ------------------------------------------------------------
+
+__global__ void split_keys(const int32_t *__restrict__ col, int64_t nnz, int32_t width,
+                           uint64_t *__restrict__ key, uint32_t *__restrict__ perm) {
+    for (int64_t k = (int64_t)blockIdx.x * kB + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * kB) {
+        key[k] = (uint64_t)(col[k] / width);
+        perm[k] = (uint32_t)k;
+    }
+}
+
+// first[q] = number of sorted keys below q, for q = 0 .. n_keys.
+__global__ void keys_first(const uint64_t *__restrict__ skey, int64_t nnz, int64_t n_keys,
+                           int32_t *__restrict__ first) {
+    for (int64_t q = (int64_t)blockIdx.x * kB + threadIdx.x; q <= n_keys;
+         q += (int64_t)gridDim.x * kB) {
+        int64_t lo = 0, hi = nnz;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (skey[mid] < (uint64_t)q) lo = mid + 1; else hi = mid;
+        }
+        first[q] = (int32_t)lo;
+    }
+}
+
+template <class V>
+__global__ void split_scatter(const uint64_t *__restrict__ skey, const uint32_t *__restrict__ perm,
+                              int64_t nnz, const int32_t *__restrict__ row,
+                              const int32_t *__restrict__ col, const V *__restrict__ val,
+                              const int32_t *__restrict__ first, const int64_t *__restrict__ start,
+                              int32_t *__restrict__ row_out, int32_t *__restrict__ col_out,
+                              V *__restrict__ val_out) {
+    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * kB) {
+        const uint64_t q = skey[i];
+        const uint32_t e = perm[i];
+        const int64_t pos = start[q] + (i - first[q]);
+        row_out[pos] = row[e];
+        col_out[pos] = col[e];
+        val_out[pos] = val[e];
+    }
+}
+
 }  // namespace
+
+void build_split(spmv_matrix_s *h, hipStream_t s) {
+    if (h->split.built) return;
+    const int32_t width = split_width(h->dt);
+    const int64_t panels = ceil_div(std::max<int64_t>(h->n_cols, 1), width);
+    const int64_t nnz = h->nnz;
+    if (panels < 2 || nnz > (int64_t)INT32_MAX / 2)
+        fail(SPMV_ERR_NOT_APPLICABLE, "column-split COO needs more than %d columns", width);
+    const size_t vs = dtype_size(h->dt);
+    DevBuf keys, perm, first, dstart;
+    keys.alloc(std::max<int64_t>(nnz, 1) * 8);
+    perm.alloc(std::max<int64_t>(nnz, 1) * 4);
+    first.alloc((panels + 1) * 4);
+    if (nnz > 0) {
+        split_keys<<<grid_of_n(nnz), kB, 0, s>>>(h->col.as<int32_t>(), nnz, width,
+                                                 keys.as<uint64_t>(), perm.as<uint32_t>());
+        SPMV_CHECK_LAUNCH();
+        int bits = 0;
+        while (bits < 64 && (uint64_t)(panels - 1) >> bits) ++bits;
+        radix_sort_pairs(keys, perm, nnz, bits, s);
+    }
+    keys_first<<<grid_of_n(panels + 1), kB, 0, s>>>(keys.as<uint64_t>(), nnz, panels,
+                                                    first.as<int32_t>());
+    SPMV_CHECK_LAUNCH();
+    std::vector<int32_t> hfirst(panels + 1);
+    SPMV_HIP(hipMemcpyAsync(hfirst.data(), first.p, (panels + 1) * 4, hipMemcpyDeviceToHost, s));
+    SPMV_HIP(hipStreamSynchronize(s));
+    SplitPart P;
+    P.panels = (int32_t)panels;
+    P.width = width;
+    P.start.assign(panels + 1, 0);
+    P.count.assign(panels, 0);
+    for (int64_t p = 0; p < panels; ++p) {
+        P.count[p] = hfirst[p + 1] - hfirst[p];
+        P.start[p + 1] = P.start[p] + (P.count[p] + 3) / 4 * 4;  // 16-byte aligned panels
+    }
+    const int64_t cap = padded_count(P.start[panels]);
+    P.row.alloc(cap * 4);
+    P.col.alloc(cap * 4);
+    P.val.alloc(cap * vs);
+    SPMV_HIP(hipMemsetAsync(P.row.p, 0, cap * 4, s));
+    SPMV_HIP(hipMemsetAsync(P.col.p, 0, cap * 4, s));
+    SPMV_HIP(hipMemsetAsync(P.val.p, 0, cap * vs, s));
+    dstart.alloc((panels + 1) * 8);
+    SPMV_HIP(hipMemcpyAsync(dstart.p, P.start.data(), (panels + 1) * 8, hipMemcpyHostToDevice, s));
+    if (nnz > 0) {
+        if (h->dt == SPMV_F64)
+            split_scatter<double><<<grid_of_n(nnz), kB, 0, s>>>(
+                keys.as<uint64_t>(), perm.as<uint32_t>(), nnz, h->row.as<int32_t>(),
+                h->col.as<int32_t>(), h->val.as<double>(), first.as<int32_t>(),
+                dstart.as<int64_t>(), P.row.as<int32_t>(), P.col.as<int32_t>(), P.val.as<double>());
+        else
+            split_scatter<float><<<grid_of_n(nnz), kB, 0, s>>>(
+                keys.as<uint64_t>(), perm.as<uint32_t>(), nnz, h->row.as<int32_t>(),
+                h->col.as<int32_t>(), h->val.as<float>(), first.as<int32_t>(),
+                dstart.as<int64_t>(), P.row.as<int32_t>(), P.col.as<int32_t>(), P.val.as<float>());
+        SPMV_CHECK_LAUNCH();
+    }
+    SPMV_HIP(hipStreamSynchronize(s));
+    P.built = true;
+    h->split = std::move(P);
+}
 
 int32_t sorted_max_rows(const spmv_matrix_s *h) {
     int col_bits = 1;

@@ -117,6 +117,7 @@ double tune_format(spmv_matrix_s *h, spmv_format f, const void *x, void *y, int3
         SPMV_HIP(hipStreamSynchronize(s));
         if (h->panel.built && !variant_needs_panel(f, bi)) h->panel = PanelPart{};
         if (h->sorted.built && !variant_needs_sorted(f, bi)) h->sorted = SortedPart{};
+        if (h->split.built && !variant_needs_split(f, bi)) h->split = SplitPart{};
     }
     if (best_idx) *best_idx = bi;
     return best;

@@ -30,6 +30,8 @@ CASES = {
     "sparse_rows": lambda: synth.poisson_random(7001, 0.7, 106),
     "wide": lambda: synth.random_rect(700, 5000, 40000, 107),
     "tall": lambda: synth.random_rect(5000, 30, 9000, 108),
+    # x spans several 2 MB column panels (the column-split COO variant applies)
+    "very_wide": lambda: synth.random_rect(1500, 1_200_000, 45000, 113),
     "one_long_row": _one_long_row,
     "last_row_only": lambda: synth.from_coords("last_row_only", 4000, 4000,
                                                np.full(1000, 3999), np.arange(0, 4000, 4), 109),
