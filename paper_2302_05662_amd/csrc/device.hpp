@@ -196,49 +196,66 @@ __device__ __forceinline__ void csr_rows_pipelined(const int32_t *__restrict__ c
 }
 
 
-// Sum of one sorted block's products into an FP64 accumulator in LDS: the
-// entries [bs, be) (bs a multiple of 4) are split into NW equal slices, slice w
-// streamed by wavefront w in chunks of 64*ITEMS entries with the next chunk's
-// 16-byte loads in flight during the current chunk's x gathers. An index packs
-// the row inside the block above the low `col_bits` column bits; -1 marks
-// padding. Loads are clamped to last_load; products are added to s_y[row]
-// with local atomics (no fixed order). Every thread of the workgroup calls it.
+// Sum of one sorted block's products into an FP64 accumulator in LDS. The
+// block's stream [bs, be) holds NW equal slices (one per wavefront), each a
+// whole number of 256-entry chunks; inside a chunk the entries (sorted by
+// column) are stored transposed, lane l's 16-byte group holding entries l,
+// l+64, l+128 and l+192, so one gather instruction reads 64 consecutive
+// sorted columns (few distinct cache lines). Wavefront w streams slice w,
+// ITEMS/4 chunks per step, the next step's 16-byte loads in flight during the
+// current step's x gathers. An index packs the row inside the block above the
+// low `col_bits` column bits; -1 marks padding. Loads are clamped to
+// last_load and anything past the slice is masked. Products are added to
+// s_y[row] with local atomics (no fixed order). Every thread calls it.
+constexpr int kSortedChunk = 256;
+
 template <class V, int ITEMS, int NW>
 __device__ __forceinline__ void sorted_block_sum(const int32_t *__restrict__ idx,
                                                  const V *__restrict__ val,
                                                  const V *__restrict__ x, int64_t bs, int64_t be,
                                                  int col_bits, int64_t last_load, double *s_y) {
-    constexpr int CH = kWave * ITEMS;
+    static_assert(ITEMS % 4 == 0, "whole chunks per step");
+    constexpr int SUB = ITEMS / 4;
+    constexpr int CH = kSortedChunk * SUB;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
     const uint32_t col_mask = (1u << col_bits) - 1;
-    const int64_t per = ((be - bs + NW - 1) / NW + 3) & ~int64_t(3);
-    const int64_t start = std::min(be, bs + per * w), end = std::min(be, start + per);
-    using CI = Pack<int32_t, ITEMS>;
-    using CV = Pack<V, ITEMS>;
-    auto load = [&](int64_t q, CI &c, CV &v) {
-        const int64_t e = std::min<int64_t>(q + ITEMS * lane, last_load);
-        c = ld_i32<ITEMS>(idx + e);
-        v = ld_val<ITEMS>(val + e);
-    };
-    auto step = [&](int64_t q, const CI &c, const CV &v, CI &cn, CV &vn) {
-        V xv[ITEMS];
-        bool ok[ITEMS];
+    const int64_t per = (be - bs) / NW;
+    const int64_t start = bs + per * w, end = start + per;
+    using CI = Pack<int32_t, 4>;
+    using CV = Pack<V, 4>;
+    auto load = [&](int64_t q, CI (&c)[SUB], CV (&v)[SUB]) {
 #pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            ok[j] = (q + ITEMS * lane + j < end) && c.v[j] != -1;
-            xv[j] = x[ok[j] ? ((uint32_t)c.v[j] & col_mask) : 0u];
+        for (int u = 0; u < SUB; ++u) {
+            const int64_t e = std::min<int64_t>(q + u * kSortedChunk + 4 * lane, last_load);
+            c[u] = ld_i32<4>(idx + e);
+            v[u] = ld_val<4>(val + e);
         }
+    };
+    auto step = [&](int64_t q, const CI (&c)[SUB], const CV (&v)[SUB], CI (&cn)[SUB],
+                    CV (&vn)[SUB]) {
+        V xv[SUB][4];
+        bool ok[SUB][4];
+#pragma unroll
+        for (int u = 0; u < SUB; ++u)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                ok[u][j] = (q + u * kSortedChunk < end) && c[u].v[j] != -1;
+                xv[u][j] = x[ok[u][j] ? ((uint32_t)c[u].v[j] & col_mask) : 0u];
+            }
         __builtin_amdgcn_sched_barrier(0);
         load(q + CH, cn, vn);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int j = 0; j < ITEMS; ++j)
-            if (ok[j])
-                atomicAdd(&s_y[(uint32_t)c.v[j] >> col_bits], (double)v.v[j] * (double)xv[j]);
+        for (int u = 0; u < SUB; ++u)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (ok[u][j])
+                    atomicAdd(&s_y[(uint32_t)c[u].v[j] >> col_bits],
+                              (double)v[u].v[j] * (double)xv[u][j]);
     };
-    CI cA, cB;
-    CV vA, vB;
+    CI cA[SUB], cB[SUB];
+    CV vA[SUB], vB[SUB];
     load(start, cA, vA);
     for (int64_t q = start;;) {  // two steps per pass: the chunk buffers alternate
         if (q >= end) break;

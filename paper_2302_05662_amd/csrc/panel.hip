@@ -20,8 +20,9 @@
 //
 // The sorted-block COO kernel goes further: a workgroup owns a block of up to
 // 4096 rows whose entries are sorted by column, and its 16 wavefronts stream
-// equal slices of them. The 64 lanes of one gather then read nearby columns
-// and share cache lines (on a uniformly random matrix with ~33 entries per row
+// equal slices of them, each 256-entry chunk stored transposed so that one
+// gather instruction reads 64 consecutive sorted entries. Those lanes read
+// nearby columns and share cache lines (on a uniformly random matrix with ~33 entries per row
 // and 256 blocks, about 4 entries per 128-byte line of x), so a gather moves a
 // quarter of the lines a row-ordered kernel moves. Each product is added to
 // the row's FP64 accumulator in LDS with a local atomic; the order in which
@@ -227,6 +228,30 @@ __global__ void sorted_keys(const int32_t *__restrict__ row, const int32_t *__re
     }
 }
 
+// first[b] = entries of the blocks before b; padded[b] = block b's stored
+// length: kSortedWaves slices of a whole number of chunks each.
+__global__ void sorted_blocks(const int32_t *__restrict__ row_ptr, int32_t n_rows, int64_t blocks,
+                              int32_t rows, int32_t *__restrict__ first,
+                              int32_t *__restrict__ padded) {
+    for (int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x; t <= blocks;
+         t += (int64_t)gridDim.x * kB) {
+        const int64_t r0 = std::min<int64_t>(t * rows, n_rows);
+        first[t] = row_ptr[r0];
+        int32_t len = 0;
+        if (t < blocks) {
+            const int64_t r1 = std::min<int64_t>((t + 1) * rows, n_rows);
+            const int64_t cnt = row_ptr[r1] - row_ptr[r0];
+            const int64_t slice = (cnt + kSortedWaves - 1) / kSortedWaves;
+            const int64_t per = (slice + kSortedChunk - 1) / kSortedChunk * kSortedChunk;
+            len = (int32_t)(per * kSortedWaves);
+        }
+        padded[t] = len;
+    }
+}
+
+// Entry k of block b (in column order) goes to slice k / per at offset o = k % per,
+// transposed inside its 256-entry chunk: row-major (64 lanes x 4) storage of the
+// column-major order, so lane l's 16-byte group holds entries l, l+64, l+128, l+192.
 template <class V>
 __global__ void sorted_scatter(const uint32_t *__restrict__ perm, int64_t nnz,
                                const int32_t *__restrict__ row, const int32_t *__restrict__ col,
@@ -237,7 +262,11 @@ __global__ void sorted_scatter(const uint32_t *__restrict__ perm, int64_t nnz,
         const uint32_t e = perm[i];
         const int32_t r = row[e];
         const int64_t b = r / rows;
-        const int64_t pos = (int64_t)start[b] + (i - first[b]);
+        const int64_t per = ((int64_t)start[b + 1] - start[b]) / kSortedWaves;
+        const int64_t k = i - first[b];
+        const int64_t o = k % per, rr = o % kSortedChunk;
+        const int64_t pos = (int64_t)start[b] + (k / per) * per + (o - rr) +
+                            (rr % kWave) * 4 + rr / kWave;
         idx_out[pos] = (int32_t)(((uint32_t)(r % rows) << col_bits) | (uint32_t)col[e]);
         val_out[pos] = val[e];
     }
@@ -250,7 +279,7 @@ void launch_sorted(const spmv_matrix_s *h, double alpha, const void *x, double b
     const int64_t cap = padded_count(P.stream);
     coo_sorted_kernel<V, ITEMS><<<P.blocks, kST, 0, s>>>(
         h->n_rows, P.rows, P.col_bits, P.blk_ptr.as<int32_t>(), P.idx.as<int32_t>(), P.val.as<V>(),
-        cap - ITEMS, (const V *)x, (V)alpha, (V)beta, (V *)y);
+        cap - 4, (const V *)x, (V)alpha, (V)beta, (V *)y);
     SPMV_CHECK_LAUNCH();
 }
 
@@ -400,9 +429,9 @@ void build_sorted_into(const spmv_matrix_s *h, int32_t rows, SortedPart &P, hipS
     DevBuf keys, perm, first, start;
     first.alloc((blocks + 1) * 4);
     start.alloc((blocks + 1) * 4);
-    panel_groups<<<grid_of_n(blocks + 1), kB, 0, s>>>(h->row_ptr.as<int32_t>(), h->n_rows, blocks,
-                                                      P.rows, first.as<int32_t>(),
-                                                      start.as<int32_t>());
+    sorted_blocks<<<grid_of_n(blocks + 1), kB, 0, s>>>(h->row_ptr.as<int32_t>(), h->n_rows, blocks,
+                                                       P.rows, first.as<int32_t>(),
+                                                       start.as<int32_t>());
     SPMV_CHECK_LAUNCH();
     exclusive_scan_i32(start.as<int32_t>(), start.as<int32_t>(), blocks + 1, s);
     int32_t total = 0;
