@@ -748,6 +748,7 @@ template <class V> void coo_panel_4(const Args &a) { panel_spmv(a.h, 4, a.alpha,
 template <class V> void coo_panel_8(const Args &a) { panel_spmv(a.h, 8, a.alpha, a.x, a.beta, a.y, a.s); }
 template <class V> void coo_sorted_4(const Args &a) { sorted_spmv(a.h, 4, a.alpha, a.x, a.beta, a.y, a.s); }
 template <class V> void coo_sorted_8(const Args &a) { sorted_spmv(a.h, 8, a.alpha, a.x, a.beta, a.y, a.s); }
+template <class V> void coo_sorted_16(const Args &a) { sorted_spmv(a.h, 16, a.alpha, a.x, a.beta, a.y, a.s); }
 template <class V> void coo_split_4(const Args &a) { coo_split_launch<V, 4>(a); }
 template <class V> void coo_split_8(const Args &a) { coo_split_launch<V, 8>(a); }
 template <class V> void ell_1_1(const Args &a) { ell_launch<V, 1, 1>(a); }
@@ -824,6 +825,7 @@ const std::vector<Variant> &table(spmv_format f) {
         VP(SPMV_KERNEL_COO_PANEL, 512, 8, 4, 1, coo_panel_8),
         VP(SPMV_KERNEL_COO_SORTED, 1024, 4, 4, 1, coo_sorted_4),
         VP(SPMV_KERNEL_COO_SORTED, 1024, 8, 4, 1, coo_sorted_8),
+        VP(SPMV_KERNEL_COO_SORTED, 1024, 16, 4, 1, coo_sorted_16),
         VN(SPMV_KERNEL_COO_SPLIT, 256, 4, 1, 4, coo_split_4),
         VN(SPMV_KERNEL_COO_SPLIT, 256, 8, 1, 4, coo_split_8),
     };

@@ -476,10 +476,12 @@ void sorted_spmv(const spmv_matrix_s *h, int items, double alpha, const void *x,
     if (h->n_rows == 0) return;
     if (h->dt == SPMV_F64) {
         if (items == 4) launch_sorted<double, 4>(h, alpha, x, beta, y, s);
-        else launch_sorted<double, 8>(h, alpha, x, beta, y, s);
+        else if (items == 8) launch_sorted<double, 8>(h, alpha, x, beta, y, s);
+        else launch_sorted<double, 16>(h, alpha, x, beta, y, s);
     } else {
         if (items == 4) launch_sorted<float, 4>(h, alpha, x, beta, y, s);
-        else launch_sorted<float, 8>(h, alpha, x, beta, y, s);
+        else if (items == 8) launch_sorted<float, 8>(h, alpha, x, beta, y, s);
+        else launch_sorted<float, 16>(h, alpha, x, beta, y, s);
     }
 }
 
