@@ -20,7 +20,7 @@
 // more entries gets a tile of its own reduced by the whole workgroup), which
 // keeps power-law rows from setting the tail. A third tiling uses the batch's
 // own sorted-block COO copy of every matrix (blocks of up to 4096 rows, entries
-// sorted by column): a tile is one block, taken by a 1024-thread workgroup, and
+// sorted by column, the row packed in the index or held in 16 bits beside it): a tile is one block, taken by a 1024-thread workgroup, and
 // tiles are handed out largest first.
 #include <algorithm>
 #include <cmath>
@@ -37,6 +37,7 @@ constexpr int kMaxBatch = 8192;
 constexpr int kBlockRow = 8;          // lanes_log2 value meaning "the whole workgroup"
 constexpr int32_t kLongRow = 2048;    // entries from which a row gets its own tile
 constexpr int kSortedBlock = kSortedWaves * kWave;  // workgroup size of the sorted tiling
+constexpr int32_t kBatchSortedRows = 4096;          // rows per sorted block at most
 
 struct BatchDesc {
     const int32_t *rp;
@@ -51,6 +52,7 @@ struct BatchDesc {
     const int32_t *sblk;
     const int32_t *sidx;
     const void *sval;
+    const uint16_t *srows16;  // rows inside the block, or null when packed in sidx
     int64_t slast;  // last 16-byte-aligned load position of the copy
     int32_t srows, scol_bits;
 };
@@ -147,9 +149,15 @@ __global__ __launch_bounds__(kSortedBlock) void batch_sorted_kernel(
         const int nr = (int)std::min<int64_t>(d.srows, d.n_rows - row0);
         for (int i = threadIdx.x; i < nr; i += kSortedBlock) s_y[i] = 0.0;
         __syncthreads();
-        sorted_block_sum<V, ITEMS, kSortedWaves>(d.sidx, (const V *)d.sval, (const V *)d.x,
-                                                 d.sblk[tl.row_begin], d.sblk[tl.row_begin + 1],
-                                                 d.scol_bits, d.slast, s_y);
+        const int64_t bs = d.sblk[tl.row_begin], be = d.sblk[tl.row_begin + 1];
+        if (d.srows16)
+            sorted_block_sum<V, ITEMS, kSortedWaves, true>(d.sidx, d.srows16, (const V *)d.sval,
+                                                           (const V *)d.x, bs, be, d.scol_bits,
+                                                           d.slast, s_y);
+        else
+            sorted_block_sum<V, ITEMS, kSortedWaves, false>(d.sidx, nullptr, (const V *)d.sval,
+                                                            (const V *)d.x, bs, be, d.scol_bits,
+                                                            d.slast, s_y);
         __syncthreads();
         for (int i = threadIdx.x; i < nr; i += kSortedBlock)
             store_y((V *)d.y, row0 + i, s_y[i], (V)d.alpha, (V)d.beta);
@@ -263,8 +271,12 @@ void upload_desc(spmv_batch_s *b, hipStream_t s) {
 void ensure_sorted(spmv_batch_s *b, hipStream_t s) {
     if (!b->sorted.empty()) return;
     std::vector<SortedPart> parts(b->hs.size());
-    for (size_t m = 0; m < b->hs.size(); ++m)
-        build_sorted_into(b->hs[m], sorted_max_rows(b->hs[m]), parts[m], s);
+    for (size_t m = 0; m < b->hs.size(); ++m) {
+        // blocks of 4096 rows (fewer if the packed index holds at least 1024)
+        const int32_t packed = sorted_packed_rows(b->hs[m]);
+        const int32_t rows = std::min(kBatchSortedRows, packed >= 1024 ? packed : kBatchSortedRows);
+        build_sorted_into(b->hs[m], std::min(rows, sorted_max_rows(b->hs[m])), parts[m], s);
+    }
     b->sorted = std::move(parts);
     for (size_t m = 0; m < b->hs.size(); ++m) {
         const SortedPart &P = b->sorted[m];
@@ -272,6 +284,7 @@ void ensure_sorted(spmv_batch_s *b, hipStream_t s) {
         d.sblk = P.blk_ptr.as<int32_t>();
         d.sidx = P.idx.as<int32_t>();
         d.sval = P.val.p;
+        d.srows16 = P.rows16.as<uint16_t>();
         d.slast = padded_count(P.stream) - 8;  // covers 4 and 8 entries per lane
         d.srows = P.rows;
         d.scol_bits = P.col_bits;

@@ -130,18 +130,22 @@ struct PanelPart {
 
 // Column-sorted copy of the COO entries for the sorted-block COO kernel: rows
 // are cut into blocks of `rows` consecutive rows (one workgroup each); a block's
-// entries are stored contiguously sorted by column (then row) and padded to a
-// multiple of 4 with index kPanelPad and value 0. An index packs the row inside
-// the block above the column: (row % rows) << col_bits | col, with col_bits the
-// bit length of n_cols. blk_ptr[b] .. blk_ptr[b + 1] is block b's stream.
+// entries are stored sorted by column (then row) in whole 256-entry chunks,
+// each transposed (see sorted_block_sum), padding with index kPanelPad and
+// value 0. An index packs the row inside the
+// block above the column, (row % rows) << col_bits | col with col_bits the bit
+// length of n_cols, when the rows fit the bits left; otherwise (row16) the
+// index is the column and the row inside the block is a uint16 in rows16.
+// blk_ptr[b] .. blk_ptr[b + 1] is block b's stream.
 constexpr int kSortedWaves = 16;     // wavefronts per workgroup
-constexpr int kSortedRowsMax = 4096; // rows per block at most (LDS accumulators)
+constexpr int kSortedRowsMax = 8192; // rows per block at most (LDS accumulators)
 
 struct SortedPart {
     bool built = false;
+    bool row16 = false;
     int32_t rows = 0, blocks = 0, col_bits = 0;
     int64_t stream = 0;
-    DevBuf idx, val, blk_ptr;
+    DevBuf idx, val, blk_ptr, rows16;
 };
 
 // Column-split copy of the COO entries: entries ordered by column panel (2 MB
@@ -203,6 +207,8 @@ void panel_spmv(const spmv_matrix_s *h, int items, double alpha, const void *x, 
 void build_sorted(spmv_matrix_s *h, hipStream_t s);
 // Tallest sorted block the packing allows for this matrix (NOT_APPLICABLE if none).
 int32_t sorted_max_rows(const spmv_matrix_s *h);
+// Rows per block that the packed index can hold (0: none); taller blocks use rows16.
+int32_t sorted_packed_rows(const spmv_matrix_s *h);
 // Build a sorted-block copy with blocks of `rows` rows into P (used by the batch).
 void build_sorted_into(const spmv_matrix_s *h, int32_t rows, SortedPart &P, hipStream_t s);
 void build_split(spmv_matrix_s *h, hipStream_t s);  // NOT_APPLICABLE below two panels

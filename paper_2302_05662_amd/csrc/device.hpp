@@ -197,20 +197,27 @@ __device__ __forceinline__ void csr_rows_pipelined(const int32_t *__restrict__ c
 
 
 // Sum of one sorted block's products into an FP64 accumulator in LDS. The
-// block's stream [bs, be) holds NW equal slices (one per wavefront), each a
-// whole number of 256-entry chunks; inside a chunk the entries (sorted by
-// column) are stored transposed, lane l's 16-byte group holding entries l,
-// l+64, l+128 and l+192, so one gather instruction reads 64 consecutive
-// sorted columns (few distinct cache lines). Wavefront w streams slice w,
-// ITEMS/4 chunks per step, the next step's 16-byte loads in flight during the
-// current step's x gathers. An index packs the row inside the block above the
-// low `col_bits` column bits; -1 marks padding. Loads are clamped to
-// last_load and anything past the slice is masked. Products are added to
-// s_y[row] with local atomics (no fixed order). Every thread calls it.
+// block's stream [bs, be) is a whole number of 256-entry chunks in column
+// order; inside a chunk the entries are stored transposed, lane l's 16-byte
+// group holding entries l, l+64, l+128 and l+192, so one gather instruction
+// reads 64 consecutive sorted columns (few distinct cache lines). A step is
+// ITEMS/4 consecutive chunks and the NW wavefronts take steps in turn (wave w:
+// steps w, w + NW, ...), so the block moves through the columns together and
+// the x lines it needs at one time span a narrow window: the blocks on one XCD,
+// started together, share that window in its L2. The next step's 16-byte loads
+// are in flight during the current step's x gathers. An index packs the row
+// inside the block above the low `col_bits` column bits (ROW16: the index is
+// the column and the row is the uint16 at the same position of rows16); -1
+// marks padding. Loads are clamped to last_load and chunks past be are masked.
+// Products are added to s_y[row] with local atomics (no fixed order). Every
+// thread calls it.
 constexpr int kSortedChunk = 256;
 
-template <class V, int ITEMS, int NW>
+typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+
+template <class V, int ITEMS, int NW, bool ROW16>
 __device__ __forceinline__ void sorted_block_sum(const int32_t *__restrict__ idx,
+                                                 const uint16_t *__restrict__ rows16,
                                                  const V *__restrict__ val,
                                                  const V *__restrict__ x, int64_t bs, int64_t be,
                                                  int col_bits, int64_t last_load, double *s_y) {
@@ -220,50 +227,57 @@ __device__ __forceinline__ void sorted_block_sum(const int32_t *__restrict__ idx
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
     const uint32_t col_mask = (1u << col_bits) - 1;
-    const int64_t per = (be - bs) / NW;
-    const int64_t start = bs + per * w, end = start + per;
+    constexpr int64_t STRIDE = (int64_t)CH * NW;
+    const int64_t start = bs + (int64_t)CH * w, end = be;
     using CI = Pack<int32_t, 4>;
     using CV = Pack<V, 4>;
-    auto load = [&](int64_t q, CI (&c)[SUB], CV (&v)[SUB]) {
+    struct Chunk {
+        CI c[SUB];
+        CV v[SUB];
+        u16x4 r[SUB];
+    };
+    auto load = [&](int64_t q, Chunk &k) {
 #pragma unroll
         for (int u = 0; u < SUB; ++u) {
             const int64_t e = std::min<int64_t>(q + u * kSortedChunk + 4 * lane, last_load);
-            c[u] = ld_i32<4>(idx + e);
-            v[u] = ld_val<4>(val + e);
+            k.c[u] = ld_i32<4>(idx + e);
+            k.v[u] = ld_val<4>(val + e);
+            if constexpr (ROW16) k.r[u] = __builtin_nontemporal_load((const u16x4 *)(rows16 + e));
         }
     };
-    auto step = [&](int64_t q, const CI (&c)[SUB], const CV (&v)[SUB], CI (&cn)[SUB],
-                    CV (&vn)[SUB]) {
+    auto step = [&](int64_t q, const Chunk &k, Chunk &kn) {
         V xv[SUB][4];
         bool ok[SUB][4];
 #pragma unroll
         for (int u = 0; u < SUB; ++u)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                ok[u][j] = (q + u * kSortedChunk < end) && c[u].v[j] != -1;
-                xv[u][j] = x[ok[u][j] ? ((uint32_t)c[u].v[j] & col_mask) : 0u];
+                ok[u][j] = (q + u * kSortedChunk < end) && k.c[u].v[j] != -1;
+                const uint32_t col = ROW16 ? (uint32_t)k.c[u].v[j] : ((uint32_t)k.c[u].v[j] & col_mask);
+                xv[u][j] = x[ok[u][j] ? col : 0u];
             }
         __builtin_amdgcn_sched_barrier(0);
-        load(q + CH, cn, vn);
+        load(q + STRIDE, kn);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < SUB; ++u)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                if (ok[u][j])
-                    atomicAdd(&s_y[(uint32_t)c[u].v[j] >> col_bits],
-                              (double)v[u].v[j] * (double)xv[u][j]);
+                if (ok[u][j]) {
+                    const uint32_t row =
+                        ROW16 ? (uint32_t)k.r[u][j] : ((uint32_t)k.c[u].v[j] >> col_bits);
+                    atomicAdd(&s_y[row], (double)k.v[u].v[j] * (double)xv[u][j]);
+                }
     };
-    CI cA[SUB], cB[SUB];
-    CV vA[SUB], vB[SUB];
-    load(start, cA, vA);
+    Chunk kA, kB;
+    load(start, kA);
     for (int64_t q = start;;) {  // two steps per pass: the chunk buffers alternate
         if (q >= end) break;
-        step(q, cA, vA, cB, vB);
-        q += CH;
+        step(q, kA, kB);
+        q += STRIDE;
         if (q >= end) break;
-        step(q, cB, vB, cA, vA);
-        q += CH;
+        step(q, kB, kA);
+        q += STRIDE;
     }
 }
 

@@ -19,8 +19,8 @@
 // y = alpha * s + beta * y.
 //
 // The sorted-block COO kernel goes further: a workgroup owns a block of up to
-// 4096 rows whose entries are sorted by column, and its 16 wavefronts stream
-// equal slices of them, each 256-entry chunk stored transposed so that one
+// 8192 rows whose entries are sorted by column, and its 16 wavefronts stream
+// its chunks in turn, each 256-entry chunk stored transposed so that one
 // gather instruction reads 64 consecutive sorted entries. Those lanes read
 // nearby columns and share cache lines (on a uniformly random matrix with ~33 entries per row
 // and 256 blocks, about 4 entries per 128-byte line of x), so a gather moves a
@@ -203,22 +203,25 @@ void launch_panel(const spmv_matrix_s *h, double alpha, const void *x, double be
 
 constexpr int kST = kSortedWaves * kWave;
 
-template <class V, int ITEMS>
+template <class V, int ITEMS, bool ROW16>
 __global__ __launch_bounds__(kST) void coo_sorted_kernel(
     int32_t n_rows, int32_t rows, int32_t col_bits, const int32_t *__restrict__ blk_ptr,
-    const int32_t *__restrict__ idx, const V *__restrict__ val, int64_t last_load,
-    const V *__restrict__ x, V alpha, V beta, V *__restrict__ y) {
+    const int32_t *__restrict__ idx, const uint16_t *__restrict__ rows16,
+    const V *__restrict__ val, int64_t last_load, const V *__restrict__ x, V alpha, V beta,
+    V *__restrict__ y) {
     __shared__ double s_y[kSortedRowsMax];
     const int64_t row0 = (int64_t)blockIdx.x * rows;
     const int nr = (int)std::min<int64_t>(rows, n_rows - row0);
     for (int i = threadIdx.x; i < nr; i += kST) s_y[i] = 0.0;
     __syncthreads();
-    sorted_block_sum<V, ITEMS, kSortedWaves>(idx, val, x, blk_ptr[blockIdx.x],
-                                             blk_ptr[blockIdx.x + 1], col_bits, last_load, s_y);
+    sorted_block_sum<V, ITEMS, kSortedWaves, ROW16>(idx, rows16, val, x, blk_ptr[blockIdx.x],
+                                                    blk_ptr[blockIdx.x + 1], col_bits, last_load,
+                                                    s_y);
     __syncthreads();
     for (int i = threadIdx.x; i < nr; i += kST) store_y(y, row0 + i, s_y[i], alpha, beta);
 }
 
+// key = (block << col_bits) | col: a block's entries sort together, by column.
 __global__ void sorted_keys(const int32_t *__restrict__ row, const int32_t *__restrict__ col,
                             int64_t nnz, int32_t rows, int32_t col_bits, uint64_t *__restrict__ key,
                             uint32_t *__restrict__ perm) {
@@ -229,7 +232,7 @@ __global__ void sorted_keys(const int32_t *__restrict__ row, const int32_t *__re
 }
 
 // first[b] = entries of the blocks before b; padded[b] = block b's stored
-// length: kSortedWaves slices of a whole number of chunks each.
+// length: a whole number of chunks.
 __global__ void sorted_blocks(const int32_t *__restrict__ row_ptr, int32_t n_rows, int64_t blocks,
                               int32_t rows, int32_t *__restrict__ first,
                               int32_t *__restrict__ padded) {
@@ -241,33 +244,36 @@ __global__ void sorted_blocks(const int32_t *__restrict__ row_ptr, int32_t n_row
         if (t < blocks) {
             const int64_t r1 = std::min<int64_t>((t + 1) * rows, n_rows);
             const int64_t cnt = row_ptr[r1] - row_ptr[r0];
-            const int64_t slice = (cnt + kSortedWaves - 1) / kSortedWaves;
-            const int64_t per = (slice + kSortedChunk - 1) / kSortedChunk * kSortedChunk;
-            len = (int32_t)(per * kSortedWaves);
+            len = (int32_t)((cnt + kSortedChunk - 1) / kSortedChunk * kSortedChunk);
         }
         padded[t] = len;
     }
 }
 
-// Entry k of block b (in column order) goes to slice k / per at offset o = k % per,
-// transposed inside its 256-entry chunk: row-major (64 lanes x 4) storage of the
-// column-major order, so lane l's 16-byte group holds entries l, l+64, l+128, l+192.
+// Entry k of block b (in column order) goes to chunk k / 256, transposed inside
+// it: row-major (64 lanes x 4) storage of the column-major order, so lane l's
+// 16-byte group holds entries l, l+64, l+128, l+192.
+// With rows16 set, the index is the column and the row inside the block goes to
+// rows16 at the same position.
 template <class V>
 __global__ void sorted_scatter(const uint32_t *__restrict__ perm, int64_t nnz,
                                const int32_t *__restrict__ row, const int32_t *__restrict__ col,
                                const V *__restrict__ val, const int32_t *__restrict__ first,
                                const int32_t *__restrict__ start, int32_t rows, int32_t col_bits,
-                               int32_t *__restrict__ idx_out, V *__restrict__ val_out) {
+                               int32_t *__restrict__ idx_out, uint16_t *__restrict__ rows16,
+                               V *__restrict__ val_out) {
     for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * kB) {
         const uint32_t e = perm[i];
         const int32_t r = row[e];
         const int64_t b = r / rows;
-        const int64_t per = ((int64_t)start[b + 1] - start[b]) / kSortedWaves;
-        const int64_t k = i - first[b];
-        const int64_t o = k % per, rr = o % kSortedChunk;
-        const int64_t pos = (int64_t)start[b] + (k / per) * per + (o - rr) +
-                            (rr % kWave) * 4 + rr / kWave;
-        idx_out[pos] = (int32_t)(((uint32_t)(r % rows) << col_bits) | (uint32_t)col[e]);
+        const int64_t k = i - first[b], rr = k % kSortedChunk;
+        const int64_t pos = (int64_t)start[b] + (k - rr) + (rr % kWave) * 4 + rr / kWave;
+        if (rows16) {
+            idx_out[pos] = col[e];
+            rows16[pos] = (uint16_t)(r % rows);
+        } else {
+            idx_out[pos] = (int32_t)(((uint32_t)(r % rows) << col_bits) | (uint32_t)col[e]);
+        }
         val_out[pos] = val[e];
     }
 }
@@ -277,9 +283,15 @@ void launch_sorted(const spmv_matrix_s *h, double alpha, const void *x, double b
                    hipStream_t s) {
     const SortedPart &P = h->sorted;
     const int64_t cap = padded_count(P.stream);
-    coo_sorted_kernel<V, ITEMS><<<P.blocks, kST, 0, s>>>(
-        h->n_rows, P.rows, P.col_bits, P.blk_ptr.as<int32_t>(), P.idx.as<int32_t>(), P.val.as<V>(),
-        cap - 4, (const V *)x, (V)alpha, (V)beta, (V *)y);
+    if (P.row16)
+        coo_sorted_kernel<V, ITEMS, true><<<P.blocks, kST, 0, s>>>(
+            h->n_rows, P.rows, P.col_bits, P.blk_ptr.as<int32_t>(), P.idx.as<int32_t>(),
+            P.rows16.as<uint16_t>(), P.val.as<V>(), cap - 4, (const V *)x, (V)alpha, (V)beta,
+            (V *)y);
+    else
+        coo_sorted_kernel<V, ITEMS, false><<<P.blocks, kST, 0, s>>>(
+            h->n_rows, P.rows, P.col_bits, P.blk_ptr.as<int32_t>(), P.idx.as<int32_t>(), nullptr,
+            P.val.as<V>(), cap - 4, (const V *)x, (V)alpha, (V)beta, (V *)y);
     SPMV_CHECK_LAUNCH();
 }
 
@@ -388,13 +400,24 @@ void build_split(spmv_matrix_s *h, hipStream_t s) {
     h->split = std::move(P);
 }
 
-int32_t sorted_max_rows(const spmv_matrix_s *h) {
+namespace {
+int sorted_col_bits(const spmv_matrix_s *h) {
     int col_bits = 1;
     while ((int64_t(1) << col_bits) <= h->n_cols) ++col_bits;  // n_cols < 2^col_bits
-    const int row_bits = 32 - col_bits;
-    if (row_bits < 1 || h->nnz > (int64_t)INT32_MAX / 2)
-        fail(SPMV_ERR_NOT_APPLICABLE, "sorted-block COO cannot pack %d columns", h->n_cols);
-    return (int32_t)std::min<int64_t>(kSortedRowsMax, int64_t(1) << std::min(row_bits, 30));
+    return col_bits;
+}
+}  // namespace
+
+int32_t sorted_max_rows(const spmv_matrix_s *h) {
+    if (h->nnz > (int64_t)INT32_MAX / 2)
+        fail(SPMV_ERR_NOT_APPLICABLE, "sorted-block COO holds at most 2^30 entries, not %lld",
+             (long long)h->nnz);
+    return kSortedRowsMax;
+}
+
+int32_t sorted_packed_rows(const spmv_matrix_s *h) {
+    const int row_bits = 32 - sorted_col_bits(h);
+    return row_bits < 1 ? 0 : (int32_t)std::min<int64_t>(kSortedRowsMax, int64_t(1) << row_bits);
 }
 
 void build_sorted(spmv_matrix_s *h, hipStream_t s) {
@@ -417,11 +440,11 @@ void build_sorted_into(const spmv_matrix_s *h, int32_t rows, SortedPart &P, hipS
     const int32_t max_rows = sorted_max_rows(h);
     if (rows < 1 || rows > max_rows) fail(SPMV_ERR_INVALID_ARG, "bad sorted block height %d", rows);
     const int64_t n = h->n_rows, nnz = h->nnz;
-    int col_bits = 1;
-    while ((int64_t(1) << col_bits) <= h->n_cols) ++col_bits;
+    const int col_bits = sorted_col_bits(h);
     P = SortedPart{};
     P.col_bits = col_bits;
     P.rows = rows;
+    P.row16 = rows > sorted_packed_rows(h);
     P.blocks = (int32_t)ceil_div(n, P.rows);
     const int64_t blocks = P.blocks;
     const size_t vs = dtype_size(h->dt);
@@ -443,6 +466,10 @@ void build_sorted_into(const spmv_matrix_s *h, int32_t rows, SortedPart &P, hipS
     P.val.alloc(cap * vs);
     SPMV_HIP(hipMemsetAsync(P.idx.p, 0xFF, cap * 4, s));  // kPanelPad
     SPMV_HIP(hipMemsetAsync(P.val.p, 0, cap * vs, s));
+    if (P.row16) {
+        P.rows16.alloc(cap * 2);
+        SPMV_HIP(hipMemsetAsync(P.rows16.p, 0, cap * 2, s));
+    }
     if (nnz > 0) {
         keys.alloc(nnz * 8);
         perm.alloc(nnz * 4);
@@ -457,12 +484,12 @@ void build_sorted_into(const spmv_matrix_s *h, int32_t rows, SortedPart &P, hipS
             sorted_scatter<double><<<grid_of_n(nnz), kB, 0, s>>>(
                 perm.as<uint32_t>(), nnz, h->row.as<int32_t>(), h->col.as<int32_t>(),
                 h->val.as<double>(), first.as<int32_t>(), start.as<int32_t>(), P.rows, col_bits,
-                P.idx.as<int32_t>(), P.val.as<double>());
+                P.idx.as<int32_t>(), P.rows16.as<uint16_t>(), P.val.as<double>());
         else
             sorted_scatter<float><<<grid_of_n(nnz), kB, 0, s>>>(
                 perm.as<uint32_t>(), nnz, h->row.as<int32_t>(), h->col.as<int32_t>(),
                 h->val.as<float>(), first.as<int32_t>(), start.as<int32_t>(), P.rows, col_bits,
-                P.idx.as<int32_t>(), P.val.as<float>());
+                P.idx.as<int32_t>(), P.rows16.as<uint16_t>(), P.val.as<float>());
         SPMV_CHECK_LAUNCH();
     }
     P.blk_ptr = std::move(start);

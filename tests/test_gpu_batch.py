@@ -24,6 +24,8 @@ def _matrices():
     ms.append(synth.from_coords("no_entries", 50, 50, [], [], 10))
     ms.append(synth.random_rect(10, 4000, 9000, 11))  # ten rows of ~900 entries
     ms.append(synth.power_law(3000, 12, cap=3000, value_dist="uniform"))  # rows past 2048
+    # columns too wide for a packed row index: sorted blocks keep 16-bit rows beside them
+    ms.append(synth.random_rect(5000, (1 << 22) + 9, 20000, 13))
     return ms
 
 

@@ -238,3 +238,37 @@ def test_reordered_coo_layouts_at_their_column_limits():
     yd = torch.zeros(n_rows, dtype=torch.float32, device="cuda")
     var, _ = S.spmv_tune(h, S.SPMV_FMT_COO, xd, yd, reps=2, flush=False)
     assert kinds[var] != "coo_panel"
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_sorted_block_rows_beside_wide_columns(dtype):
+    """Columns too wide to leave the block's rows any room in the packed index: the
+    sorted-block layout keeps the row inside the block in 16 bits beside the column."""
+    n_rows, n_cols = 20011, (1 << 26) + 3
+    rng = np.random.default_rng(31)
+    lengths = rng.integers(0, 9, n_rows)
+    lengths[[0, 777, n_rows - 1]] = [0, 0, 6]  # empty rows and a full last row
+    rows = np.repeat(np.arange(n_rows), lengths)
+    cols = np.concatenate([np.sort(rng.choice(n_cols, k, replace=False)) for k in lengths])
+    cols[-1] = n_cols - 1
+    m = synth.from_coords("wide_rows16", n_rows, n_cols, rows, cols, 32)
+    print(f"[spmv rows16] n_cols={n_cols} nnz={m.nnz} {dtype.__name__}", flush=True)
+    v = m.values(dtype)
+    x = synth.uniform_vector(n_cols, dtype, [32, 3])
+    y0 = synth.uniform_vector(n_rows, dtype, [32, 4])
+    a, b = 0.75, -1.25
+    c = OF.canonicalize(n_rows, n_cols, m.row, m.col, v)
+    y_ref = OS.spmv_csr(c["row_ptr"], c["col"], c["val"], x, dtype(a), dtype(b), y0)
+    den = OS.row_denominator(c["row_ptr"], c["col"], c["val"], x, dtype(a), dtype(b), y0)
+    h = S.spmv_create(m.n_rows, m.n_cols, m.row, m.col, v)
+    xd = torch.from_numpy(x).cuda()
+    sorted_vars = [i for i in range(S.spmv_variant_count(S.SPMV_FMT_COO, h.dtype_code))
+                   if S.spmv_variant_describe(S.SPMV_FMT_COO, h.dtype_code, i)["kernel"] == "coo_sorted"]
+    assert sorted_vars
+    for var in sorted_vars:
+        S.spmv_set_variant(h, S.SPMV_FMT_COO, var)
+        yd = torch.from_numpy(y0.copy()).cuda()
+        S.spmv_run(h, S.SPMV_FMT_COO, a, xd, b, yd)
+        err = OS.max_row_error(yd.cpu().numpy(), y_ref, den)
+        assert err <= C.TOL[dtype], (var, err)
+    del xd
