@@ -84,7 +84,8 @@ def kernel_symbols(fmt, info, dtype="float"):
     if info["kernel"] == "coo_panel":
         return [f"coo_panel_kernel<{dtype}, {l}>"]
     if info["kernel"] == "coo_sorted":
-        return [f"coo_sorted_kernel<{dtype}, {l}>"]
+        # the third template argument (16-bit rows or packed) depends on the matrix
+        return [f"coo_sorted_kernel<{dtype}, {l}, "]
     if info["kernel"] == "coo_split":
         return [f"coo_tile_kernel<{dtype}, {b}, {l}, false>", f"coo_tile_kernel<{dtype}, {b}, {l}, true>"]
     if info["kernel"] == "coo":
