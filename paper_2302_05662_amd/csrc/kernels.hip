@@ -264,6 +264,11 @@ __global__ __launch_bounds__(64 * KS) void ell_ksplit_kernel(int32_t n_rows, int
 }
 
 // ---- ELL: RPT consecutive rows per thread, column-major slots ----------------------
+//
+// Slots are taken UNROLL at a time: the group's index and value loads are all
+// issued first (a slot past K is not loaded), then every x gather of the group,
+// then the products, so a thread waits for one load latency and one gather
+// latency per group. Products are added in slot order.
 
 template <class V, int BLOCK, int RPT, int UNROLL>
 __global__ __launch_bounds__(BLOCK) void ell_kernel(int32_t n_rows, int32_t K, int32_t pitch,
@@ -277,31 +282,40 @@ __global__ __launch_bounds__(BLOCK) void ell_kernel(int32_t n_rows, int32_t K, i
     double acc[RPT];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) acc[q] = 0.0;
-    int32_t k = 0;
-    if constexpr (UNROLL > 1) {
-        for (; k + UNROLL <= K; k += UNROLL) {
-            Pack<int32_t, RPT> c[UNROLL];
-            Pack<V, RPT> v[UNROLL];
+    for (int32_t k = 0; k < K; k += UNROLL) {
+        Pack<int32_t, RPT> c[UNROLL];
+        Pack<V, RPT> v[UNROLL];
 #pragma unroll
-            for (int u = 0; u < UNROLL; ++u) {
+        for (int u = 0; u < UNROLL; ++u) {
+            if (k + u < K) {  // uniform across the wavefront
                 const int64_t off = (int64_t)(k + u) * pitch + i0;
                 c[u] = ld_i32<RPT>(ecol + off);
                 v[u] = ld_val<RPT>(evals + off);
+            } else {
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) {
+                    c[u].v[q] = -1;
+                    v[u].v[q] = V(0);
+                }
             }
-#pragma unroll
-            for (int u = 0; u < UNROLL; ++u)
-#pragma unroll
-                for (int q = 0; q < RPT; ++q)
-                    if (c[u].v[q] >= 0) acc[q] += (double)v[u].v[q] * (double)x[c[u].v[q]];
         }
-    }
-    for (; k < K; ++k) {
-        const int64_t off = (int64_t)k * pitch + i0;
-        Pack<int32_t, RPT> c = ld_i32<RPT>(ecol + off);
-        Pack<V, RPT> v = ld_val<RPT>(evals + off);
+        V xv[UNROLL][RPT];
+        bool ok[UNROLL][RPT];
 #pragma unroll
-        for (int q = 0; q < RPT; ++q)
-            if (c.v[q] >= 0) acc[q] += (double)v.v[q] * (double)x[c.v[q]];
+        for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                ok[u][q] = c[u].v[q] >= 0;
+                xv[u][q] = x[ok[u][q] ? c[u].v[q] : 0];
+            }
+        __builtin_amdgcn_sched_barrier(0);  // every gather of the group before the products
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const double sum = acc[q] + (double)v[u].v[q] * (double)xv[u][q];
+                acc[q] = ok[u][q] ? sum : acc[q];
+            }
     }
 #pragma unroll
     for (int q = 0; q < RPT; ++q)
@@ -757,6 +771,10 @@ template <class V> void ell_2_1(const Args &a) { ell_launch<V, 2, 1>(a); }
 template <class V> void ell_2_2(const Args &a) { ell_launch<V, 2, 2>(a); }
 template <class V> void ell_4_1(const Args &a) { ell_launch<V, 4, 1>(a); }
 template <class V> void ell_4_2(const Args &a) { ell_launch<V, 4, 2>(a); }
+template <class V> void ell_1_8(const Args &a) { ell_launch<V, 1, 8>(a); }
+template <class V> void ell_2_8(const Args &a) { ell_launch<V, 2, 8>(a); }
+template <class V> void ell_4_4(const Args &a) { ell_launch<V, 4, 4>(a); }
+template <class V> void ell_4_8(const Args &a) { ell_launch<V, 4, 8>(a); }
 template <class V> void hyb_1_4(const Args &a) { hyb_launch<V, 1, 4>(a); }
 template <class V> void hyb_1_8(const Args &a) { hyb_launch<V, 1, 8>(a); }
 template <class V> void hyb_2_4(const Args &a) { hyb_launch<V, 2, 4>(a); }
@@ -838,6 +856,8 @@ const std::vector<Variant> &table(spmv_format f) {
         VP(SPMV_KERNEL_ELL, 256, 2, 2, 2, ell_q2), VP(SPMV_KERNEL_ELL, 256, 4, 4, 2, ell_q4),
         VK(SPMV_KERNEL_ELL, 128, 2, 2, ell_k2_2), VK(SPMV_KERNEL_ELL, 256, 1, 4, ell_k4_1),
         VK(SPMV_KERNEL_ELL, 256, 2, 4, ell_k4_2), VK(SPMV_KERNEL_ELL, 256, 4, 4, ell_k4_4),
+        VN(SPMV_KERNEL_ELL, 256, 1, 8, 1, ell_1_8), VN(SPMV_KERNEL_ELL, 256, 2, 8, 2, ell_2_8),
+        VN(SPMV_KERNEL_ELL, 256, 4, 4, 4, ell_4_4), VN(SPMV_KERNEL_ELL, 256, 4, 8, 4, ell_4_8),
     };
     static const std::vector<Variant> hyb = {
         VN(SPMV_KERNEL_HYB, 256, 1, 4, 1, hyb_1_4), VN(SPMV_KERNEL_HYB, 256, 1, 8, 1, hyb_1_8),
