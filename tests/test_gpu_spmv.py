@@ -272,3 +272,36 @@ def test_sorted_block_rows_beside_wide_columns(dtype):
         err = OS.max_row_error(yd.cpu().numpy(), y_ref, den)
         assert err <= C.TOL[dtype], (var, err)
     del xd
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_sorted_blocks_with_long_rows_and_empty_runs(dtype):
+    """Sorted-block COO with a few rows of 9K-20K entries (thousands of local atomic adds
+    to one accumulator), scattered short rows and a run of 30K empty rows."""
+    n_rows, n_cols = 100_003, 40_009
+    rng = np.random.default_rng(51)
+    lengths = np.zeros(n_rows, np.int64)
+    lengths[rng.choice(n_rows, 3000, replace=False)] = rng.integers(1, 6, 3000)
+    lengths[[7, 50_000, 50_001, n_rows - 1]] = [20_000, 15_000, 9, 12_000]
+    lengths[60_000:90_000] = 0
+    rows = np.repeat(np.arange(n_rows), lengths)
+    cols = np.concatenate([np.sort(rng.choice(n_cols, k, replace=False)) for k in lengths])
+    m = synth.from_coords("long_rows_empty_runs", n_rows, n_cols, rows, cols, 52)
+    print(f"[spmv long rows] nnz={m.nnz} {dtype.__name__}", flush=True)
+    v = m.values(dtype)
+    x = synth.uniform_vector(n_cols, dtype, [52, 3])
+    y0 = synth.uniform_vector(n_rows, dtype, [52, 4])
+    a, b = -1.5, 0.5
+    c = OF.canonicalize(n_rows, n_cols, m.row, m.col, v)
+    y_ref = OS.spmv_csr(c["row_ptr"], c["col"], c["val"], x, dtype(a), dtype(b), y0)
+    den = OS.row_denominator(c["row_ptr"], c["col"], c["val"], x, dtype(a), dtype(b), y0)
+    h = S.spmv_create(m.n_rows, m.n_cols, m.row, m.col, v)
+    xd = torch.from_numpy(x).cuda()
+    sorted_vars = [i for i in range(S.spmv_variant_count(S.SPMV_FMT_COO, h.dtype_code))
+                   if S.spmv_variant_describe(S.SPMV_FMT_COO, h.dtype_code, i)["kernel"] == "coo_sorted"]
+    for var in sorted_vars:
+        S.spmv_set_variant(h, S.SPMV_FMT_COO, var)
+        yd = torch.from_numpy(y0.copy()).cuda()
+        S.spmv_run(h, S.SPMV_FMT_COO, a, xd, b, yd)
+        err = OS.max_row_error(yd.cpu().numpy(), y_ref, den)
+        assert err <= C.TOL[dtype], (var, err)
