@@ -300,11 +300,20 @@ def ingest_unsorted(S, torch, synth, tune=True):
         per[FMT_NAMES[fmt]] = {"us": round(ms * 1e3, 1), "useful_gbps": round(useful / ms / 1e6, 1),
                                "gflops": round(2 * m.nnz / ms / 1e6, 1), "kernel": info["kernel"],
                                "lanes": info["lanes"], "block": info["block"]}
+    # CSR scalar against CSR vector at each lane count: the best variant of each
+    csr_by_lanes = {}
+    for var in range(S.spmv_variant_count(S.SPMV_FMT_CSR, S.SPMV_F32)):
+        info = S.spmv_variant_describe(S.SPMV_FMT_CSR, S.SPMV_F32, var)
+        key = "scalar" if info["kernel"] == "csr_scalar" else f"vector_lanes_{info['lanes']}"
+        t = float(np.median(S.spmv_time(h, S.SPMV_FMT_CSR, x, y, variant=var, warmup=1, reps=3,
+                                        flush=True))) * 1e3
+        csr_by_lanes[key] = min(csr_by_lanes.get(key, float("inf")), round(t, 1))
     S.spmv_destroy(h)
     ok = {k: v for k, v in per.items() if v is not None}
     best = min(ok, key=lambda k: ok[k]["us"])
     power_law = {"matrix": f"{m.name}: {m.n_rows} rows, {m.nnz} entries, row lengths Zipf-like "
                            f"(mean 16, cap 50000), FP32", "per_format_tuned_cold": per,
+                 "csr_us_by_kernel": csr_by_lanes,
                  "best": best, "best_frac_of_peak": round(ok[best]["useful_gbps"] / HBM_PEAK_GBPS, 4)}
     return rates, power_law
 

@@ -14,7 +14,8 @@ For each matrix (the 2-D Laplacian and the four single-SpMV families, seeds from
 Results go to an ``.npz`` file that is rewritten every ``save_every`` matrices;
 an interrupted collection resumes from it (seeds already present are skipped).
 
-Usage: python -m paper_2302_05662_amd.selector_data OUT.npz FIRST_SEED LAST_SEED
+Usage: python -m paper_2302_05662_amd.selector_data OUT.npz FIRST_SEED LAST_SEED [--with-powerlaw]
+(--with-powerlaw draws from the extended family set that adds the power law.)
 """
 from __future__ import annotations
 
@@ -40,7 +41,7 @@ def _save(path, rec):
     os.replace(tmp, path)
 
 
-def collect(path, seeds, tune_reps=3, check_reps=5, save_every=25, log=print):
+def collect(path, seeds, tune_reps=3, check_reps=5, save_every=25, log=print, families=None):
     import torch
 
     import paper_2302_05662_amd as S
@@ -51,7 +52,8 @@ def collect(path, seeds, tune_reps=3, check_reps=5, save_every=25, log=print):
     done = set(int(s) for s in rec["seed"])
     todo = [s for s in seeds if s not in done]
     t0 = time.perf_counter()
-    for i, spec in enumerate(synth.config5_specs(todo)):
+    fams = synth.CFG5_FAMILIES if families is None else families
+    for i, spec in enumerate(synth.config5_specs(todo, families=fams)):
         m = synth.config5_matrix(spec)
         h = S.spmv_create(m.n_rows, m.n_cols, m.row, m.col, m.values(np.float32))
         feats = S.spmv_features(h)
@@ -88,4 +90,7 @@ def collect(path, seeds, tune_reps=3, check_reps=5, save_every=25, log=print):
 
 if __name__ == "__main__":
     out, first, last = sys.argv[1], int(sys.argv[2]), int(sys.argv[3])
-    collect(out, list(range(first, last + 1)), log=lambda s: print(s, flush=True))
+    import synth as _synth
+
+    fams = _synth.CFG5X_FAMILIES if "--with-powerlaw" in sys.argv[4:] else None
+    collect(out, list(range(first, last + 1)), log=lambda s: print(s, flush=True), families=fams)

@@ -10,6 +10,11 @@ majority class.
 
 Usage: python -m paper_2302_05662_amd.selector_fit DATA.npz [DATA2.npz ...]
 writes selector_model.npy and selector_eval.json next to this file.
+
+python -m paper_2302_05662_amd.selector_fit --extended DATA.npz EXT.npz evaluates, on a
+set that adds the power-law family (seeds 7000-7599), the installed network and one
+retrained on both training splits; it writes selector_eval_extended.json and
+selector_model_extended.npy and leaves the installed network alone.
 """
 from __future__ import annotations
 
@@ -85,7 +90,65 @@ def fit(d, seed=5, epochs=200):
     return model.cpu().numpy(), ev
 
 
+def _eval(pred, y, tc, fam=None, only=None):
+    sel = np.ones(len(y), bool) if only is None else (fam == only)
+    if not sel.any():
+        return None
+    return {"matrices": int(sel.sum()), "accuracy": float(np.mean(pred[sel] == y[sel])),
+            **scores(pred[sel], tc[sel])}
+
+
+def fit_extended(d, dx, seed=5, epochs=200):
+    """The installed network and one retrained with the power-law family, on both held-out sets."""
+    import torch
+
+    import paper_2302_05662_amd as S
+    import synth
+
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    tr = (d["seed"] >= TRAIN_SEEDS[0]) & (d["seed"] <= TRAIN_SEEDS[1])
+    he = (d["seed"] >= HELDOUT_SEEDS[0]) & (d["seed"] <= HELDOUT_SEEDS[1])
+    trx = (dx["seed"] >= synth.CFG5X_TRAIN[0]) & (dx["seed"] <= synth.CFG5X_TRAIN[-1])
+    hex_ = (dx["seed"] >= synth.CFG5X_HELDOUT[0]) & (dx["seed"] <= synth.CFG5X_HELDOUT[-1])
+    sets = {"heldout": (d, he), "extended_heldout": (dx, hex_)}
+
+    def predict(model, dd):
+        applicable = np.isfinite(dd["t_check"]).astype(np.uint8)
+        _, cls = S.spmv_selector_predict(model, dev(dd["feats"].astype(np.float32)),
+                                         applicable=dev(applicable))
+        return cls.cpu().numpy()
+
+    installed = dev(np.load(MODEL_PATH, allow_pickle=False))
+    F = np.concatenate([d["feats"][tr], dx["feats"][trx]]).astype(np.float32)
+    y = np.concatenate([labels_of(d["t_label"][tr]), labels_of(dx["t_label"][trx])])
+    retrained = S.spmv_selector_train(dev(F), dev(y), dev(synth.glorot_params(seed)),
+                                      dev(synth.epoch_permutations(seed, len(y), epochs)),
+                                      epochs=epochs)
+    ev = {"extended_families": list(synth.CFG5X_FAMILIES),
+          "extended_train_matrices": int(trx.sum()), "extended_heldout_matrices": int(hex_.sum()),
+          "extended_label_histogram": np.bincount(labels_of(dx["t_label"]), minlength=4).tolist(),
+          "retrained_on": int(len(y))}
+    for name, model in (("installed", installed), ("retrained", retrained)):
+        for sname, (dd, m) in sets.items():
+            pred = predict(model, dd)[m]
+            yy, tc, fam = labels_of(dd["t_label"])[m], dd["t_check"][m], dd["family"][m]
+            ev[f"{name}_on_{sname}"] = _eval(pred, yy, tc)
+            ev[f"{name}_on_{sname}_powerlaw"] = _eval(pred, yy, tc, fam, "powerlaw")
+    for sname, (dd, m) in sets.items():
+        tc = dd["t_check"][m]
+        ev[f"always_csr_on_{sname}"] = scores(np.zeros(int(m.sum()), np.int64), tc)
+        ev[f"rule_on_{sname}"] = scores(dd["rule"][m].astype(np.int64), tc)
+    return retrained.cpu().numpy(), ev
+
+
 if __name__ == "__main__":
+    if sys.argv[1] == "--extended":
+        model, ev = fit_extended(load([sys.argv[2]]), load([sys.argv[3]]))
+        np.save(os.path.join(HERE, "selector_model_extended.npy"), model)
+        with open(os.path.join(HERE, "selector_eval_extended.json"), "w") as fh:
+            json.dump(ev, fh, indent=1)
+        print(json.dumps(ev, indent=1))
+        sys.exit(0)
     data = load(sys.argv[1:])
     model, ev = fit(data)
     np.save(MODEL_PATH, model)

@@ -24,5 +24,9 @@ from .matrices import (  # noqa: F401
     uniform_vector,
     random_rect,
     from_coords,
+    CFG5_FAMILIES,
+    CFG5X_FAMILIES,
+    CFG5X_TRAIN,
+    CFG5X_HELDOUT,
 )
 from .mlp_inputs import glorot_params, epoch_permutations  # noqa: F401

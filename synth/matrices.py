@@ -313,14 +313,21 @@ def config4_matrix(spec: dict) -> Matrix:
 CFG5_TRAIN = tuple(range(5000, 6500))
 CFG5_HELDOUT = tuple(range(6500, 7000))
 CFG5_NNZ_CAP = 20_000_000
+CFG5_FAMILIES = ("laplacian2d", "banded", "random", "blockdiag", "stencil3d")
+# extended selector set: the same families plus the power law of the load-imbalanced config
+CFG5X_FAMILIES = CFG5_FAMILIES + ("powerlaw",)
+CFG5X_TRAIN = tuple(range(7000, 7400))
+CFG5X_HELDOUT = tuple(range(7400, 7600))
 
 
-def config5_specs(seeds, n_lo: float = 4096, n_hi: float = 2e6, nnz_cap: int = CFG5_NNZ_CAP) -> list:
-    """Selector matrices: 2-D Laplacians and the four single-SpMV families, nnz <= cap."""
+def config5_specs(seeds, n_lo: float = 4096, n_hi: float = 2e6, nnz_cap: int = CFG5_NNZ_CAP,
+                  families=CFG5_FAMILIES) -> list:
+    """Selector matrices: 2-D Laplacians and the four single-SpMV families (optionally the
+    power law too), nnz <= cap."""
     out = []
     for s in seeds:
         rng = np.random.default_rng(s)
-        fam = ("laplacian2d", "banded", "random", "blockdiag", "stencil3d")[int(rng.integers(5))]
+        fam = families[int(rng.integers(len(families)))]
         n = _log_uniform_int(rng, n_lo, n_hi)
         if fam == "laplacian2d":
             g = int(min(1400, max(64, round(math.sqrt(n)))))
@@ -335,6 +342,9 @@ def config5_specs(seeds, n_lo: float = 4096, n_hi: float = 2e6, nnz_cap: int = C
             out.append({"seed": s, "family": fam, "n": n, "lam": lam})
         elif fam == "blockdiag":
             out.append({"seed": s, "family": fam, "n": max(8, n // 8 * 8), "bs": 8})
+        elif fam == "powerlaw":  # mean row length 16
+            n = int(min(n, nnz_cap // 16))
+            out.append({"seed": s, "family": fam, "n": n, "cap": min(50_000, n), "dist": "uniform"})
         else:
             g = int(min(125, max(16, round(n ** (1.0 / 3.0)))))
             out.append({"seed": s, "family": fam, "g": g, "n": g ** 3})

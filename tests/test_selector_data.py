@@ -65,3 +65,30 @@ def test_oracle_training_on_the_data_reaches_the_same_quality(data):
     pred, _ = OM.predict(theta, mean, std, data["feats"][held], applicable=app)
     assert (pred == data["label"][held]).mean() >= 0.9
     assert _regret(pred, data["t_check"][held]).mean() <= 0.05
+
+
+EXT = os.path.join(PKG, "selector_data_ext_mi355x.npz")
+
+
+def test_extended_set_with_the_power_law_family():
+    """The extended set (seeds 7000-7599, the power law added): the installed network has
+    never seen that family; the one retrained with it keeps its regret low there."""
+    d = dict(np.load(EXT, allow_pickle=False))
+    assert d["feats"].shape == (600, 12)
+    specs = synth.config5_specs(d["seed"][:12].tolist(), families=synth.CFG5X_FAMILIES)
+    assert [s["family"] for s in specs] == d["family"][:12].tolist()
+    held = d["seed"] >= synth.CFG5X_HELDOUT[0]
+    t = d["t_check"][held]
+    app = np.isfinite(t)
+    ev = json.load(open(os.path.join(PKG, "selector_eval_extended.json")))
+    regrets = {}
+    for name, path in (("installed", MODEL), ("retrained", os.path.join(PKG, "selector_model_extended.npy"))):
+        model = np.load(path).astype(np.float64)
+        pred, _ = OM.predict(model[:5252], model[5252:5264], model[5264:5276], d["feats"][held],
+                             applicable=app)
+        regrets[name] = _regret(pred, t)
+        assert abs(ev[f"{name}_on_extended_heldout"]["mean_regret"] - regrets[name].mean()) < 0.01
+    pl = d["family"][held] == "powerlaw"
+    assert pl.sum() >= 20
+    assert regrets["retrained"].mean() <= 0.05
+    assert regrets["retrained"][pl].mean() < regrets["installed"][pl].mean()
