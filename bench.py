@@ -72,6 +72,8 @@ def kernel_symbols(fmt, info, dtype="float"):
     b, l, u, v, pp = info["block"], info["lanes"], info["unroll"], info["vec"], info["pipelined"]
     if info["kernel"] == "csr_scalar":
         return [f"csr_scalar_kernel<{dtype}, {b}, {u}>"]
+    if info["kernel"] == "csr_stream":
+        return [f"csr_stream_kernel<{dtype}, {b}>"]
     if info["kernel"] == "csr_vector" and pp:
         return [f"csr_pipe_kernel<{dtype}, {b}, {l}, {pp}>"]
     if info["kernel"] == "ell" and info.get("ksplit", 1) > 1:

@@ -71,10 +71,17 @@ typedef enum spmv_kernel {
                                    16 waves: the order of the FP64 additions, and
                                    so the last bits of a result, may vary between
                                    runs; second copy of the entries as above      */
-    SPMV_KERNEL_COO_SPLIT = 7   /* tiled COO run once per 2 MB column panel of x
+    SPMV_KERNEL_COO_SPLIT = 7,  /* tiled COO run once per 2 MB column panel of x
                                    over a copy ordered by (panel, row, column), the
                                    first pass writing y, the others adding; only
                                    for matrices with more than one panel          */
+    SPMV_KERNEL_CSR_STREAM = 8  /* CSR over row blocks of at most 256 rows and
+                                   2048 entries: a workgroup streams its block's
+                                   entries with 16-byte loads, keeps the products
+                                   in LDS and sums each row there in order (a row
+                                   too long for the stage gets a workgroup of its
+                                   own); the row blocks are computed on the host
+                                   by spmv_set_variant / spmv_tune / spmv_time    */
 } spmv_kernel;
 
 typedef enum spmv_select_mode {

@@ -132,6 +132,7 @@ bool prepare_variant(spmv_matrix_s *h, spmv_format f, int32_t idx, hipStream_t s
     const bool panel = variant_needs_panel(f, idx) && !h->panel.built;
     const bool sorted = variant_needs_sorted(f, idx) && !h->sorted.built;
     const bool split = variant_needs_split(f, idx) && !h->split.built;
+    if (variant_needs_csr_blocks(f, idx) && !h->csr_blocks.built) build_csr_blocks(h, s);
     if (!panel && !sorted && !split) return true;
     try {
         if (panel) build_panel(h, s);

@@ -166,6 +166,20 @@ struct RowStats {
 
 }  // namespace spmv
 
+namespace spmv {
+// Row blocks of the CSR stream kernel: block b = rows [rows[b], rows[b + 1]),
+// at most kCsrStreamRows rows whose entries, counted from the 4-aligned entry
+// below the block's first, fit kCsrStreamCap; a row too long for that is a
+// block of its own.
+constexpr int kCsrStreamCap = 2048;
+constexpr int kCsrStreamRows = 256;
+struct CsrBlocks {
+    bool built = false;
+    int32_t blocks = 0;
+    DevBuf rows;
+};
+}  // namespace spmv
+
 struct spmv_matrix_s {
     int device = 0;
     int32_t n_rows = 0, n_cols = 0;
@@ -180,6 +194,7 @@ struct spmv_matrix_s {
     spmv::PanelPart panel;    // built on first use of a streaming COO variant
     spmv::SortedPart sorted;  // built on first use of a sorted-block COO variant
     spmv::SplitPart split;    // built on first use of a column-split COO variant
+    spmv::CsrBlocks csr_blocks;  // built on first use of a CSR stream variant
     spmv::RowStats stats;
     int32_t variant[SPMV_NUM_FORMATS] = {0, 0, 0, 0};
 };
@@ -222,6 +237,8 @@ int32_t default_variant(const spmv_matrix_s *h, spmv_format f);
 bool variant_needs_panel(spmv_format f, int32_t idx);
 bool variant_needs_sorted(spmv_format f, int32_t idx);
 bool variant_needs_split(spmv_format f, int32_t idx);
+bool variant_needs_csr_blocks(spmv_format f, int32_t idx);
+void build_csr_blocks(spmv_matrix_s *h, hipStream_t s);
 // Make variant idx of f runnable: builds the panel layout for a panel variant.
 // Returns false when that layout is not applicable to the matrix.
 bool prepare_variant(spmv_matrix_s *h, spmv_format f, int32_t idx, hipStream_t s);

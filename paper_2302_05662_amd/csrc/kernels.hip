@@ -124,6 +124,78 @@ __global__ __launch_bounds__(BLOCK) void csr_pipe_kernel(
                                           row0, n_rows, y, alpha, beta);
 }
 
+// ---- CSR stream: row blocks staged through LDS ------------------------------------
+//
+// Workgroup b takes row block b. Its entries, from the 4-aligned entry at or
+// below the block's first, are loaded 4 at a time with 16-byte loads (threads
+// take consecutive groups, so a wave reads 1 KB contiguous per value array);
+// each product v * x[col] is formed in FP64 and kept in LDS, and after a barrier
+// thread t adds row t's products in entry order and writes y. A block holding a
+// single row longer than the stage instead has every thread accumulate every
+// BLOCK*4-th group and the partial sums are added in a fixed tree.
+
+template <class V, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void csr_stream_kernel(const int32_t *__restrict__ blk_rows,
+                                                           const int32_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ col,
+                                                           const V *__restrict__ val,
+                                                           const V *__restrict__ x, V alpha, V beta,
+                                                           V *__restrict__ y) {
+    constexpr int CAP = kCsrStreamCap;
+    static_assert(CAP % (4 * BLOCK) == 0, "whole 16-byte groups per thread");
+    __shared__ double s_p[CAP];
+    __shared__ double s_w[BLOCK / kWave];
+    const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int32_t r0 = blk_rows[b], r1 = blk_rows[b + 1];
+    const int64_t e0 = rp[r0], e1 = rp[r1];
+    const int64_t base = e0 & ~int64_t(3);
+    if (e1 - base <= CAP) {
+#pragma unroll
+        for (int g = 0; g < CAP / (4 * BLOCK); ++g) {
+            const int64_t q = base + (int64_t)(g * BLOCK + threadIdx.x) * 4;
+            if (q < e1) {
+                const Pack<int32_t, 4> c = ld_i32<4>(col + q);
+                const Pack<V, 4> v = ld_val<4>(val + q);
+                V xv[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const bool ok = q + j >= e0 && q + j < e1;
+                    xv[j] = x[ok ? c.v[j] : 0];
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    s_p[q - base + j] = (double)v.v[j] * (double)xv[j];
+            }
+        }
+        __syncthreads();
+        for (int32_t t = threadIdx.x; t < r1 - r0; t += BLOCK) {
+            const int64_t a0 = rp[r0 + t] - base, a1 = rp[r0 + t + 1] - base;
+            double s = 0.0;
+            for (int64_t k = a0; k < a1; ++k) s += s_p[k];
+            store_y(y, r0 + t, s, alpha, beta);
+        }
+        return;
+    }
+    double s = 0.0;  // one long row: r1 == r0 + 1
+    for (int64_t q = base + (int64_t)threadIdx.x * 4; q < e1; q += (int64_t)BLOCK * 4) {
+        const Pack<int32_t, 4> c = ld_i32<4>(col + q);
+        const Pack<V, 4> v = ld_val<4>(val + q);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (q + j >= e0 && q + j < e1) s += (double)v.v[j] * (double)x[c.v[j]];
+    }
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) s += __shfl_down(s, d, kWave);
+    if (threadIdx.x % kWave == 0) s_w[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < BLOCK / kWave; ++w) t += s_w[w];
+        store_y(y, r0, t, alpha, beta);
+    }
+}
+
 // ---- ELL, software pipelined: the next slot's loads are in flight during the
 // current slot's x gathers --------------------------------------------------------
 
@@ -641,6 +713,17 @@ void csr_pipe_launch(const Args &a) {
     SPMV_CHECK_LAUNCH();
 }
 
+template <class V, int BLOCK>
+void csr_stream_launch(const Args &a) {
+    const spmv_matrix_s *h = a.h;
+    if (h->n_rows == 0) return;
+    if (!h->csr_blocks.built) fail(SPMV_ERR_NOT_CONVERTED, "CSR stream row blocks not built");
+    csr_stream_kernel<V, BLOCK><<<h->csr_blocks.blocks, BLOCK, 0, a.s>>>(
+        h->csr_blocks.rows.as<int32_t>(), h->row_ptr.as<int32_t>(), h->col.as<int32_t>(),
+        h->val.as<V>(), (const V *)a.x, (V)a.alpha, (V)a.beta, (V *)a.y);
+    SPMV_CHECK_LAUNCH();
+}
+
 template <class V, int RPT, int DEPTH>
 void ell_pipe_launch(const Args &a) {
     const spmv_matrix_s *h = a.h;
@@ -765,6 +848,8 @@ template <class V> void coo_sorted_8(const Args &a) { sorted_spmv(a.h, 8, a.alph
 template <class V> void coo_sorted_16(const Args &a) { sorted_spmv(a.h, 16, a.alpha, a.x, a.beta, a.y, a.s); }
 template <class V> void coo_split_4(const Args &a) { coo_split_launch<V, 4>(a); }
 template <class V> void coo_split_8(const Args &a) { coo_split_launch<V, 8>(a); }
+template <class V> void csr_stream_256(const Args &a) { csr_stream_launch<V, 256>(a); }
+template <class V> void csr_stream_512(const Args &a) { csr_stream_launch<V, 512>(a); }
 template <class V> void ell_1_1(const Args &a) { ell_launch<V, 1, 1>(a); }
 template <class V> void ell_1_2(const Args &a) { ell_launch<V, 1, 2>(a); }
 template <class V> void ell_2_1(const Args &a) { ell_launch<V, 2, 1>(a); }
@@ -834,6 +919,8 @@ const std::vector<Variant> &table(spmv_format f) {
         V4(SPMV_KERNEL_CSR_VECTOR, 128, 16, 2, csr_b128_16_2),
         V4(SPMV_KERNEL_CSR_VECTOR, 512, 16, 2, csr_b512_16_2),
         V4(SPMV_KERNEL_CSR_VECTOR, 1024, 16, 2, csr_b1024_16_2),
+        VN(SPMV_KERNEL_CSR_STREAM, 256, 1, 1, 4, csr_stream_256),
+        VN(SPMV_KERNEL_CSR_STREAM, 512, 1, 1, 4, csr_stream_512),
     };
     static const std::vector<Variant> coo = {
         VN(SPMV_KERNEL_COO, 256, 2, 1, 2, coo_2),
@@ -922,6 +1009,35 @@ bool variant_needs_panel(spmv_format f, int32_t idx) {
 bool variant_needs_split(spmv_format f, int32_t idx) {
     const auto &t = table(f);
     return idx >= 0 && idx < (int32_t)t.size() && t[idx].info.kernel == SPMV_KERNEL_COO_SPLIT;
+}
+
+bool variant_needs_csr_blocks(spmv_format f, int32_t idx) {
+    const auto &t = table(f);
+    return idx >= 0 && idx < (int32_t)t.size() && t[idx].info.kernel == SPMV_KERNEL_CSR_STREAM;
+}
+
+void build_csr_blocks(spmv_matrix_s *h, hipStream_t s) {
+    if (h->csr_blocks.built) return;
+    const int64_t n = h->n_rows;
+    std::vector<int32_t> rp(n + 1);
+    SPMV_HIP(hipMemcpyAsync(rp.data(), h->row_ptr.p, rp.size() * 4, hipMemcpyDeviceToHost, s));
+    SPMV_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> rows{0};
+    for (int64_t r = 0; r < n;) {
+        const int64_t base = rp[r] & ~int64_t(3);
+        int64_t e = r + 1;  // a row too long for the stage stays alone
+        if (rp[r + 1] - base <= kCsrStreamCap)
+            while (e < n && e - r < kCsrStreamRows && rp[e + 1] - base <= kCsrStreamCap) ++e;
+        rows.push_back((int32_t)e);
+        r = e;
+    }
+    CsrBlocks B;
+    B.blocks = (int32_t)rows.size() - 1;
+    B.rows.alloc(rows.size() * 4);
+    SPMV_HIP(hipMemcpyAsync(B.rows.p, rows.data(), rows.size() * 4, hipMemcpyHostToDevice, s));
+    SPMV_HIP(hipStreamSynchronize(s));
+    B.built = true;
+    h->csr_blocks = std::move(B);
 }
 
 bool variant_needs_sorted(spmv_format f, int32_t idx) {

@@ -36,7 +36,8 @@ STATUS_NAMES = ("OK", "INVALID_ARG", "OUT_OF_BOUNDS", "DUPLICATE", "NOT_CONVERTE
 SPMV_FMT_CSR, SPMV_FMT_COO, SPMV_FMT_ELL, SPMV_FMT_HYB = 0, 1, 2, 3
 FORMAT_NAMES = ("CSR", "COO", "ELL", "HYB")
 SPMV_F32, SPMV_F64 = 0, 1
-KERNEL_NAMES = ("csr_scalar", "csr_vector", "coo", "ell", "hyb", "coo_panel", "coo_sorted", "coo_split")
+KERNEL_NAMES = ("csr_scalar", "csr_vector", "coo", "ell", "hyb", "coo_panel", "coo_sorted", "coo_split",
+                "csr_stream")
 SPMV_SELECT_MODEL, SPMV_SELECT_EXHAUSTIVE, SPMV_SELECT_RULE = 0, 1, 2
 
 

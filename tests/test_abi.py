@@ -25,7 +25,7 @@ def test_variant_catalogue():
             n = S.spmv_variant_count(fmt, dt)
             assert n >= 3
             kinds = {S.spmv_variant_describe(fmt, dt, i)["kernel"] for i in range(n)}
-            want = {0: {"csr_scalar", "csr_vector"}, 1: {"coo", "coo_panel", "coo_sorted", "coo_split"}, 2: {"ell"}, 3: {"hyb"}}[fmt]
+            want = {0: {"csr_scalar", "csr_vector", "csr_stream"}, 1: {"coo", "coo_panel", "coo_sorted", "coo_split"}, 2: {"ell"}, 3: {"hyb"}}[fmt]
             assert kinds == want
             with pytest.raises(S.SpmvError) as e:
                 S.spmv_variant_describe(fmt, dt, n)
