@@ -776,7 +776,7 @@ void ell_ksplit_launch(const Args &a) {
 template <class V, int RPT, int ITEMS>
 void hyb_launch(const Args &a) {
     const spmv_matrix_s *h = a.h;
-    ell_arrays_launch<V, RPT, 1>(h->n_rows, h->hyb.K, h->hyb.pitch, h->hyb.ell_col.as<int32_t>(),
+    ell_arrays_launch<V, RPT, 4>(h->n_rows, h->hyb.K, h->hyb.pitch, h->hyb.ell_col.as<int32_t>(),
                                  h->hyb.ell_val.as<V>(), a);
     if (h->hyb.nnz_tail > 0)
         coo_launch_impl<V, ITEMS, true>(h->hyb.nnz_tail, h->n_rows, h->hyb.tail_row.as<int32_t>(),
@@ -856,6 +856,8 @@ template <class V> void ell_2_1(const Args &a) { ell_launch<V, 2, 1>(a); }
 template <class V> void ell_2_2(const Args &a) { ell_launch<V, 2, 2>(a); }
 template <class V> void ell_4_1(const Args &a) { ell_launch<V, 4, 1>(a); }
 template <class V> void ell_4_2(const Args &a) { ell_launch<V, 4, 2>(a); }
+template <class V> void ell_1_4(const Args &a) { ell_launch<V, 1, 4>(a); }
+template <class V> void ell_2_4(const Args &a) { ell_launch<V, 2, 4>(a); }
 template <class V> void ell_1_8(const Args &a) { ell_launch<V, 1, 8>(a); }
 template <class V> void ell_2_8(const Args &a) { ell_launch<V, 2, 8>(a); }
 template <class V> void ell_4_4(const Args &a) { ell_launch<V, 4, 4>(a); }
@@ -945,6 +947,7 @@ const std::vector<Variant> &table(spmv_format f) {
         VK(SPMV_KERNEL_ELL, 256, 2, 4, ell_k4_2), VK(SPMV_KERNEL_ELL, 256, 4, 4, ell_k4_4),
         VN(SPMV_KERNEL_ELL, 256, 1, 8, 1, ell_1_8), VN(SPMV_KERNEL_ELL, 256, 2, 8, 2, ell_2_8),
         VN(SPMV_KERNEL_ELL, 256, 4, 4, 4, ell_4_4), VN(SPMV_KERNEL_ELL, 256, 4, 8, 4, ell_4_8),
+        VN(SPMV_KERNEL_ELL, 256, 1, 4, 1, ell_1_4), VN(SPMV_KERNEL_ELL, 256, 2, 4, 2, ell_2_4),
     };
     static const std::vector<Variant> hyb = {
         VN(SPMV_KERNEL_HYB, 256, 1, 4, 1, hyb_1_4), VN(SPMV_KERNEL_HYB, 256, 1, 8, 1, hyb_1_8),

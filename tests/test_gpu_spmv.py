@@ -305,3 +305,44 @@ def test_sorted_blocks_with_long_rows_and_empty_runs(dtype):
         S.spmv_run(h, S.SPMV_FMT_COO, a, xd, b, yd)
         err = OS.max_row_error(yd.cpu().numpy(), y_ref, den)
         assert err <= C.TOL[dtype], (var, err)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_csr_stream_rows_at_the_stage_size(dtype):
+    """CSR stream row blocks: rows of 2043-2050 entries starting at every alignment (some fit
+    the 2048-entry stage with their 4-aligned start, some get a workgroup of their own),
+    runs of 1-entry rows longer than 256 rows (blocks capped at 256 rows), empty rows."""
+    lengths = []
+    for extra in range(4):  # shift the alignment of what follows
+        lengths += [extra + 1] + [2043 + extra, 2044 + extra, 2045 + extra, 2046 + extra, 2047, 2048,
+                                  2049, 2050, 0, 3]
+    lengths += [1] * 700 + [0] * 300 + [5] * 600
+    lengths = np.array(lengths, np.int64)
+    n_rows, n_cols = len(lengths), 5003
+    rng = np.random.default_rng(61)
+    rows = np.repeat(np.arange(n_rows), lengths)
+    cols = np.concatenate([np.sort(rng.choice(n_cols, k, replace=False)) for k in lengths])
+    m = synth.from_coords("stage_edges", n_rows, n_cols, rows, cols, 62)
+    print(f"[spmv csr stream edges] rows={n_rows} nnz={m.nnz} {dtype.__name__}", flush=True)
+    v = m.values(dtype)
+    x = synth.uniform_vector(n_cols, dtype, [62, 3])
+    y0 = synth.uniform_vector(n_rows, dtype, [62, 4])
+    a, b = 1.25, -0.75
+    c = OF.canonicalize(n_rows, n_cols, m.row, m.col, v)
+    y_ref = OS.spmv_csr(c["row_ptr"], c["col"], c["val"], x, dtype(a), dtype(b), y0)
+    den = OS.row_denominator(c["row_ptr"], c["col"], c["val"], x, dtype(a), dtype(b), y0)
+    h = S.spmv_create(m.n_rows, m.n_cols, m.row, m.col, v)
+    xd = torch.from_numpy(x).cuda()
+    stream = [i for i in range(S.spmv_variant_count(S.SPMV_FMT_CSR, h.dtype_code))
+              if S.spmv_variant_describe(S.SPMV_FMT_CSR, h.dtype_code, i)["kernel"] == "csr_stream"]
+    assert len(stream) == 2
+    for var in stream:
+        S.spmv_set_variant(h, S.SPMV_FMT_CSR, var)
+        for rep in range(2):  # deterministic: the same bits twice
+            yd = torch.from_numpy(y0.copy()).cuda()
+            S.spmv_run(h, S.SPMV_FMT_CSR, a, xd, b, yd)
+            got = yd.cpu().numpy()
+            if rep == 0:
+                first = got.tobytes()
+            assert got.tobytes() == first
+        assert OS.max_row_error(got, y_ref, den) <= C.TOL[dtype], var
