@@ -94,7 +94,7 @@ def kernel_symbols(fmt, info, dtype="float"):
         return [f"coo_tile_kernel<{dtype}, {b}, {l}, false>", f"coo_fixup<{dtype}, {b * l}, false>"]
     if info["kernel"] == "ell":
         return [f"ell_kernel<{dtype}, {b}, {l}, {u}>"]
-    return [f"ell_kernel<{dtype}, {b}, {l}, 1>", f"coo_tile_kernel<{dtype}, {b}, {u}, true>",
+    return [f"ell_kernel<{dtype}, {b}, {l}, 4>", f"coo_tile_kernel<{dtype}, {b}, {u}, true>",
             f"coo_fixup<{dtype}, {b * u}, true>"]
 
 
