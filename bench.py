@@ -561,10 +561,16 @@ def main():
                                                            args.batched_matrices)
 
     def group_key(e):
+        """Launches of one kernel function (all its template instances) form a group when a
+        launch is that one kernel; launches of several kernels group by exact variant."""
         info = S.spmv_variant_describe(e["fmt"], S.SPMV_F32, e["variant"][e["fmt"]])
+        syms = kernel_symbols(e["fmt"], info)
+        if len(syms) == 1:
+            fn = syms[0].split("<")[0]
+            return f"{fn}_f32", info, [f"{fn}<float, "]
         key = (f"{info['kernel']}_b{info['block']}_l{info['lanes']}_u{info['unroll']}"
                f"_v{info['vec']}_p{info['pipelined']}_k{info['ksplit']}_f32")
-        return key, info
+        return key, info, syms
 
     def new_events(n):
         return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -583,8 +589,8 @@ def main():
     kernel_ms_per_step = sum(warm)
     groups = {}
     for i, e in enumerate(mats):
-        key, info = group_key(e)
-        g = groups.setdefault(key, {"warm_ms": 0.0, "members": [], "symbols": kernel_symbols(e["fmt"], info)})
+        key, info, syms = group_key(e)
+        g = groups.setdefault(key, {"warm_ms": 0.0, "members": [], "symbols": syms})
         g["warm_ms"] += warm[i]
         g["members"].append(i)
     dom_key = max(groups, key=lambda k: groups[k]["warm_ms"])
