@@ -267,7 +267,7 @@ void upload_desc(spmv_batch_s *b, hipStream_t s) {
                             hipMemcpyHostToDevice, s));
 }
 
-// (Re)build the graph {reset counter, persistent kernel} for configuration c.
+// The batch's own sorted-block COO copy of every matrix, built on first use of tiling 2.
 void ensure_sorted(spmv_batch_s *b, hipStream_t s) {
     if (!b->sorted.empty()) return;
     std::vector<SortedPart> parts(b->hs.size());
@@ -291,6 +291,7 @@ void ensure_sorted(spmv_batch_s *b, hipStream_t s) {
     }
 }
 
+// (Re)build the graph {reset counter, persistent kernel} for configuration c.
 void build_graph(spmv_batch_s *b, const spmv_batch_config &c, hipStream_t user) {
     spmv_batch_config cc = c;
     if (cc.tiling == 2) ensure_sorted(b, user);
