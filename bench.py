@@ -302,11 +302,12 @@ def ingest_unsorted(S, torch, synth, tune=True):
         per[FMT_NAMES[fmt]] = {"us": round(ms * 1e3, 1), "useful_gbps": round(useful / ms / 1e6, 1),
                                "gflops": round(2 * m.nnz / ms / 1e6, 1), "kernel": info["kernel"],
                                "lanes": info["lanes"], "block": info["block"]}
-    # CSR scalar against CSR vector at each lane count: the best variant of each
+    # CSR scalar, CSR stream and CSR vector at each lane count: the best variant of each
     csr_by_lanes = {}
     for var in range(S.spmv_variant_count(S.SPMV_FMT_CSR, S.SPMV_F32)):
         info = S.spmv_variant_describe(S.SPMV_FMT_CSR, S.SPMV_F32, var)
-        key = "scalar" if info["kernel"] == "csr_scalar" else f"vector_lanes_{info['lanes']}"
+        key = {"csr_scalar": "scalar", "csr_stream": "stream"}.get(
+            info["kernel"], f"vector_lanes_{info['lanes']}")
         t = float(np.median(S.spmv_time(h, S.SPMV_FMT_CSR, x, y, variant=var, warmup=1, reps=3,
                                         flush=True))) * 1e3
         csr_by_lanes[key] = min(csr_by_lanes.get(key, float("inf")), round(t, 1))
