@@ -53,8 +53,10 @@ struct BatchDesc {
     const int32_t *sidx;
     const void *sval;
     const uint16_t *srows16;  // rows inside the block, or null when packed in sidx
+    const int32_t *sblk_row;  // first row of each block
     int64_t slast;  // last 16-byte-aligned load position of the copy
-    int32_t srows, scol_bits;
+    int32_t scol_bits;
+    int32_t spad;
 };
 
 struct BatchTile {
@@ -135,7 +137,7 @@ template <class V, int ITEMS>
 __global__ __launch_bounds__(kSortedBlock) void batch_sorted_kernel(
     const BatchDesc *__restrict__ desc, const BatchTile *__restrict__ tiles, int32_t n_tiles,
     int32_t *__restrict__ counter) {
-    __shared__ double s_y[kSortedRowsMax];
+    __shared__ double s_y[kBatchSortedRows];
     __shared__ int32_t s_tile;
     for (;;) {
         if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
@@ -145,8 +147,8 @@ __global__ __launch_bounds__(kSortedBlock) void batch_sorted_kernel(
         if (t >= n_tiles) break;
         const BatchTile tl = tiles[t];
         const BatchDesc d = desc[tl.matrix];
-        const int64_t row0 = (int64_t)tl.row_begin * d.srows;
-        const int nr = (int)std::min<int64_t>(d.srows, d.n_rows - row0);
+        const int64_t row0 = d.sblk_row[tl.row_begin];
+        const int nr = d.sblk_row[tl.row_begin + 1] - d.sblk_row[tl.row_begin];
         for (int i = threadIdx.x; i < nr; i += kSortedBlock) s_y[i] = 0.0;
         __syncthreads();
         const int64_t bs = d.sblk[tl.row_begin], be = d.sblk[tl.row_begin + 1];
@@ -218,9 +220,9 @@ std::vector<BatchTile> plan_tiles(spmv_batch_s *b, const spmv_batch_config &c) {
         std::vector<std::pair<int32_t, BatchTile>> sized;
         for (size_t m = 0; m < b->hs.size(); ++m) {
             const std::vector<int32_t> &rp = b->row_ptr[m];
-            const int32_t n = b->hs[m]->n_rows, rows = b->sorted[m].rows;
+            const std::vector<int32_t> &st = b->sorted[m].row_start;
             for (int32_t k = 0; k < b->sorted[m].blocks; ++k) {
-                const int32_t r0 = k * rows, r1 = std::min(n, r0 + rows);
+                const int32_t r0 = st[k], r1 = st[k + 1];
                 sized.push_back({rp[r1] - rp[r0], BatchTile{(int32_t)m, k, r1, 0}});
             }
         }
@@ -274,8 +276,13 @@ void ensure_sorted(spmv_batch_s *b, hipStream_t s) {
     for (size_t m = 0; m < b->hs.size(); ++m) {
         // blocks of 4096 rows (fewer if the packed index holds at least 1024)
         const int32_t packed = sorted_packed_rows(b->hs[m]);
-        const int32_t rows = std::min(kBatchSortedRows, packed >= 1024 ? packed : kBatchSortedRows);
-        build_sorted_into(b->hs[m], std::min(rows, sorted_max_rows(b->hs[m])), parts[m], s);
+        const int32_t rows = std::min(
+            {kBatchSortedRows, packed >= 1024 ? packed : kBatchSortedRows, sorted_max_rows(b->hs[m])});
+        const int32_t n = b->hs[m]->n_rows;
+        std::vector<int32_t> row_start;
+        for (int64_t r = 0; r < n; r += rows) row_start.push_back((int32_t)r);
+        row_start.push_back(n);
+        build_sorted_into(b->hs[m], b->row_ptr[m], row_start, parts[m], s);
     }
     b->sorted = std::move(parts);
     for (size_t m = 0; m < b->hs.size(); ++m) {
@@ -286,7 +293,7 @@ void ensure_sorted(spmv_batch_s *b, hipStream_t s) {
         d.sval = P.val.p;
         d.srows16 = P.rows16.as<uint16_t>();
         d.slast = padded_count(P.stream) - 8;  // covers 4 and 8 entries per lane
-        d.srows = P.rows;
+        d.sblk_row = P.blk_row.as<int32_t>();
         d.scol_bits = P.col_bits;
     }
 }

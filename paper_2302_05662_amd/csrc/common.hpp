@@ -129,23 +129,26 @@ struct PanelPart {
 };
 
 // Column-sorted copy of the COO entries for the sorted-block COO kernel: rows
-// are cut into blocks of `rows` consecutive rows (one workgroup each); a block's
-// entries are stored sorted by column (then row) in whole 256-entry chunks,
-// each transposed (see sorted_block_sum), padding with index kPanelPad and
-// value 0. An index packs the row inside the
-// block above the column, (row % rows) << col_bits | col with col_bits the bit
-// length of n_cols, when the rows fit the bits left; otherwise (row16) the
-// index is the column and the row inside the block is a uint16 in rows16.
-// blk_ptr[b] .. blk_ptr[b + 1] is block b's stream.
-constexpr int kSortedWaves = 16;     // wavefronts per workgroup
-constexpr int kSortedRowsMax = 8192; // rows per block at most (LDS accumulators)
+// are cut into blocks of consecutive rows, block b = rows [blk_row[b],
+// blk_row[b + 1]) (one workgroup each, at most `rows` rows); a block's entries
+// are stored sorted by column (then row) in whole 256-entry chunks, each
+// transposed (see sorted_block_sum), padding with index kPanelPad and value 0.
+// An index packs the row inside the block above the column, (row - first row)
+// << col_bits | col with col_bits the bit length of n_cols, when the tallest
+// block fits the bits left; otherwise (row16) the index is the column and the
+// row inside the block is a uint16 in rows16. blk_ptr[b] .. blk_ptr[b + 1] is
+// block b's stream; workgroup i takes block blk_order[i] (largest first).
+constexpr int kSortedWaves = 16;       // wavefronts per workgroup
+constexpr int kSortedRowsMax = 16384;  // rows per block at most (FP64 LDS accumulators)
 
 struct SortedPart {
     bool built = false;
     bool row16 = false;
-    int32_t rows = 0, blocks = 0, col_bits = 0;
+    int32_t rows = 0;  // tallest block
+    int32_t blocks = 0, col_bits = 0;
     int64_t stream = 0;
-    DevBuf idx, val, blk_ptr, rows16;
+    std::vector<int32_t> row_start;  // host copy of blk_row
+    DevBuf idx, val, blk_ptr, blk_row, blk_order, rows16;
 };
 
 // Column-split copy of the COO entries: entries ordered by column panel (2 MB
@@ -224,8 +227,15 @@ void build_sorted(spmv_matrix_s *h, hipStream_t s);
 int32_t sorted_max_rows(const spmv_matrix_s *h);
 // Rows per block that the packed index can hold (0: none); taller blocks use rows16.
 int32_t sorted_packed_rows(const spmv_matrix_s *h);
-// Build a sorted-block copy with blocks of `rows` rows into P (used by the batch).
-void build_sorted_into(const spmv_matrix_s *h, int32_t rows, SortedPart &P, hipStream_t s);
+// Block boundaries 0 = r_0 < r_1 < ... < r_B = n_rows with at most max_rows rows
+// per block: cut at equal shares of the entries, in as few whole rounds of one
+// block per CU as the height limit allows.
+std::vector<int32_t> sorted_balanced_rows(const std::vector<int32_t> &row_ptr, int32_t max_rows,
+                                          int cus);
+// Build a sorted-block copy with the given block boundaries into P; row_ptr is a
+// host copy of the matrix's row pointers.
+void build_sorted_into(const spmv_matrix_s *h, const std::vector<int32_t> &row_ptr,
+                       const std::vector<int32_t> &row_start, SortedPart &P, hipStream_t s);
 void build_split(spmv_matrix_s *h, hipStream_t s);  // NOT_APPLICABLE below two panels
 void sorted_spmv(const spmv_matrix_s *h, int items, double alpha, const void *x, double beta,
                  void *y, hipStream_t s);

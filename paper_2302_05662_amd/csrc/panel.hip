@@ -19,7 +19,7 @@
 // y = alpha * s + beta * y.
 //
 // The sorted-block COO kernel goes further: a workgroup owns a block of up to
-// 8192 rows whose entries are sorted by column, and its 16 wavefronts stream
+// 16384 rows whose entries are sorted by column, and its 16 wavefronts stream
 // its chunks in turn, each 256-entry chunk stored transposed so that one
 // gather instruction reads 64 consecutive sorted entries. Those lanes read
 // nearby columns and share cache lines (on a uniformly random matrix with ~33 entries per row
@@ -205,45 +205,56 @@ constexpr int kST = kSortedWaves * kWave;
 
 template <class V, int ITEMS, bool ROW16>
 __global__ __launch_bounds__(kST) void coo_sorted_kernel(
-    int32_t n_rows, int32_t rows, int32_t col_bits, const int32_t *__restrict__ blk_ptr,
-    const int32_t *__restrict__ idx, const uint16_t *__restrict__ rows16,
-    const V *__restrict__ val, int64_t last_load, const V *__restrict__ x, V alpha, V beta,
-    V *__restrict__ y) {
+    const int32_t *__restrict__ blk_row, const int32_t *__restrict__ blk_order, int32_t col_bits,
+    const int32_t *__restrict__ blk_ptr, const int32_t *__restrict__ idx,
+    const uint16_t *__restrict__ rows16, const V *__restrict__ val, int64_t last_load,
+    const V *__restrict__ x, V alpha, V beta, V *__restrict__ y) {
     __shared__ double s_y[kSortedRowsMax];
-    const int64_t row0 = (int64_t)blockIdx.x * rows;
-    const int nr = (int)std::min<int64_t>(rows, n_rows - row0);
+    const int32_t b = blk_order[blockIdx.x];
+    const int64_t row0 = blk_row[b];
+    const int nr = blk_row[b + 1] - blk_row[b];
     for (int i = threadIdx.x; i < nr; i += kST) s_y[i] = 0.0;
     __syncthreads();
-    sorted_block_sum<V, ITEMS, kSortedWaves, ROW16>(idx, rows16, val, x, blk_ptr[blockIdx.x],
-                                                    blk_ptr[blockIdx.x + 1], col_bits, last_load,
-                                                    s_y);
+    sorted_block_sum<V, ITEMS, kSortedWaves, ROW16>(idx, rows16, val, x, blk_ptr[b], blk_ptr[b + 1],
+                                                    col_bits, last_load, s_y);
     __syncthreads();
     for (int i = threadIdx.x; i < nr; i += kST) store_y(y, row0 + i, s_y[i], alpha, beta);
 }
 
+// Block holding row r: the last b with blk_row[b] <= r (blocks are never empty).
+__device__ __forceinline__ int32_t sorted_block_of(const int32_t *__restrict__ blk_row,
+                                                   int32_t blocks, int32_t r) {
+    int32_t lo = 0, hi = blocks - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (blk_row[mid] <= r) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 // key = (block << col_bits) | col: a block's entries sort together, by column.
 __global__ void sorted_keys(const int32_t *__restrict__ row, const int32_t *__restrict__ col,
-                            int64_t nnz, int32_t rows, int32_t col_bits, uint64_t *__restrict__ key,
+                            int64_t nnz, const int32_t *__restrict__ blk_row, int32_t blocks,
+                            int32_t col_bits, uint64_t *__restrict__ key,
                             uint32_t *__restrict__ perm) {
     for (int64_t k = (int64_t)blockIdx.x * kB + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * kB) {
-        key[k] = ((uint64_t)(row[k] / rows) << col_bits) | (uint64_t)col[k];
+        const int32_t b = sorted_block_of(blk_row, blocks, row[k]);
+        key[k] = ((uint64_t)b << col_bits) | (uint64_t)col[k];
         perm[k] = (uint32_t)k;
     }
 }
 
 // first[b] = entries of the blocks before b; padded[b] = block b's stored
 // length: a whole number of chunks.
-__global__ void sorted_blocks(const int32_t *__restrict__ row_ptr, int32_t n_rows, int64_t blocks,
-                              int32_t rows, int32_t *__restrict__ first,
-                              int32_t *__restrict__ padded) {
+__global__ void sorted_blocks(const int32_t *__restrict__ row_ptr,
+                              const int32_t *__restrict__ blk_row, int64_t blocks,
+                              int32_t *__restrict__ first, int32_t *__restrict__ padded) {
     for (int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x; t <= blocks;
          t += (int64_t)gridDim.x * kB) {
-        const int64_t r0 = std::min<int64_t>(t * rows, n_rows);
-        first[t] = row_ptr[r0];
+        first[t] = row_ptr[blk_row[t]];
         int32_t len = 0;
         if (t < blocks) {
-            const int64_t r1 = std::min<int64_t>((t + 1) * rows, n_rows);
-            const int64_t cnt = row_ptr[r1] - row_ptr[r0];
+            const int64_t cnt = row_ptr[blk_row[t + 1]] - row_ptr[blk_row[t]];
             len = (int32_t)((cnt + kSortedChunk - 1) / kSortedChunk * kSortedChunk);
         }
         padded[t] = len;
@@ -259,20 +270,22 @@ template <class V>
 __global__ void sorted_scatter(const uint32_t *__restrict__ perm, int64_t nnz,
                                const int32_t *__restrict__ row, const int32_t *__restrict__ col,
                                const V *__restrict__ val, const int32_t *__restrict__ first,
-                               const int32_t *__restrict__ start, int32_t rows, int32_t col_bits,
-                               int32_t *__restrict__ idx_out, uint16_t *__restrict__ rows16,
-                               V *__restrict__ val_out) {
+                               const int32_t *__restrict__ start,
+                               const int32_t *__restrict__ blk_row, int32_t blocks,
+                               int32_t col_bits, int32_t *__restrict__ idx_out,
+                               uint16_t *__restrict__ rows16, V *__restrict__ val_out) {
     for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * kB) {
         const uint32_t e = perm[i];
         const int32_t r = row[e];
-        const int64_t b = r / rows;
+        const int32_t b = sorted_block_of(blk_row, blocks, r);
+        const uint32_t rin = (uint32_t)(r - blk_row[b]);
         const int64_t k = i - first[b], rr = k % kSortedChunk;
         const int64_t pos = (int64_t)start[b] + (k - rr) + (rr % kWave) * 4 + rr / kWave;
         if (rows16) {
             idx_out[pos] = col[e];
-            rows16[pos] = (uint16_t)(r % rows);
+            rows16[pos] = (uint16_t)rin;
         } else {
-            idx_out[pos] = (int32_t)(((uint32_t)(r % rows) << col_bits) | (uint32_t)col[e]);
+            idx_out[pos] = (int32_t)((rin << col_bits) | (uint32_t)col[e]);
         }
         val_out[pos] = val[e];
     }
@@ -285,13 +298,14 @@ void launch_sorted(const spmv_matrix_s *h, double alpha, const void *x, double b
     const int64_t cap = padded_count(P.stream);
     if (P.row16)
         coo_sorted_kernel<V, ITEMS, true><<<P.blocks, kST, 0, s>>>(
-            h->n_rows, P.rows, P.col_bits, P.blk_ptr.as<int32_t>(), P.idx.as<int32_t>(),
-            P.rows16.as<uint16_t>(), P.val.as<V>(), cap - 4, (const V *)x, (V)alpha, (V)beta,
-            (V *)y);
+            P.blk_row.as<int32_t>(), P.blk_order.as<int32_t>(), P.col_bits,
+            P.blk_ptr.as<int32_t>(), P.idx.as<int32_t>(), P.rows16.as<uint16_t>(), P.val.as<V>(),
+            cap - 4, (const V *)x, (V)alpha, (V)beta, (V *)y);
     else
         coo_sorted_kernel<V, ITEMS, false><<<P.blocks, kST, 0, s>>>(
-            h->n_rows, P.rows, P.col_bits, P.blk_ptr.as<int32_t>(), P.idx.as<int32_t>(), nullptr,
-            P.val.as<V>(), cap - 4, (const V *)x, (V)alpha, (V)beta, (V *)y);
+            P.blk_row.as<int32_t>(), P.blk_order.as<int32_t>(), P.col_bits,
+            P.blk_ptr.as<int32_t>(), P.idx.as<int32_t>(), nullptr, P.val.as<V>(), cap - 4,
+            (const V *)x, (V)alpha, (V)beta, (V *)y);
     SPMV_CHECK_LAUNCH();
 }
 
@@ -420,46 +434,95 @@ int32_t sorted_packed_rows(const spmv_matrix_s *h) {
     return row_bits < 1 ? 0 : (int32_t)std::min<int64_t>(kSortedRowsMax, int64_t(1) << row_bits);
 }
 
+std::vector<int32_t> sorted_balanced_rows(const std::vector<int32_t> &row_ptr, int32_t max_rows,
+                                          int cus) {
+    const int64_t n = (int64_t)row_ptr.size() - 1, nnz = n > 0 ? row_ptr[n] : 0;
+    std::vector<int32_t> out;
+    for (int64_t m = 1;; ++m) {
+        const int64_t B = (int64_t)std::max(cus, 1) * m;
+        // cuts at the rows where the entry count reaches b * nnz / B ...
+        std::vector<int32_t> cut{0};
+        for (int64_t b = 1; b < B; ++b) {
+            const int64_t target = b * nnz / B;
+            const int32_t r = (int32_t)(std::lower_bound(row_ptr.begin(), row_ptr.end(), target) -
+                                        row_ptr.begin());
+            if (r > cut.back() && r < n) cut.push_back(r);
+        }
+        if (n > cut.back()) cut.push_back((int32_t)n);
+        // ... then blocks taller than max_rows split evenly
+        out.assign(1, 0);
+        for (size_t j = 1; j < cut.size(); ++j) {
+            const int64_t a = cut[j - 1], h = cut[j] - a, k = ceil_div(h, max_rows);
+            for (int64_t q = 1; q <= k; ++q) out.push_back((int32_t)(a + h * q / k));
+        }
+        if ((int64_t)out.size() - 1 <= B || m >= 64) return out;
+    }
+}
+
 void build_sorted(spmv_matrix_s *h, hipStream_t s) {
     if (h->sorted.built) return;
-    const int32_t max_rows = sorted_max_rows(h);
+    (void)sorted_max_rows(h);
     int cus = 0;
     SPMV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
-    // as few blocks as possible (more entries per line of x in a block), in whole
-    // rounds of one block per CU
-    const int64_t n = h->n_rows, ncu = std::max(cus, 1);
-    const int64_t rounds = std::max<int64_t>(1, ceil_div(n, ncu * kSortedRowsMax));
-    const int32_t rows = (int32_t)std::min<int64_t>(
-        max_rows, std::max<int64_t>(1, ceil_div(n, ncu * rounds)));
+    std::vector<int32_t> rp(h->n_rows + 1);
+    SPMV_HIP(hipMemcpyAsync(rp.data(), h->row_ptr.p, rp.size() * 4, hipMemcpyDeviceToHost, s));
+    SPMV_HIP(hipStreamSynchronize(s));
+    // equal shares of the entries (a few long rows do not make one block the
+    // slowest), as few blocks as possible, in whole rounds of one block per CU
+    const std::vector<int32_t> row_start = sorted_balanced_rows(rp, kSortedRowsMax, cus);
     SortedPart P;
-    build_sorted_into(h, rows, P, s);
+    build_sorted_into(h, rp, row_start, P, s);
     h->sorted = std::move(P);
 }
 
-void build_sorted_into(const spmv_matrix_s *h, int32_t rows, SortedPart &P, hipStream_t s) {
+void build_sorted_into(const spmv_matrix_s *h, const std::vector<int32_t> &row_ptr,
+                       const std::vector<int32_t> &row_start, SortedPart &P, hipStream_t s) {
     const int32_t max_rows = sorted_max_rows(h);
-    if (rows < 1 || rows > max_rows) fail(SPMV_ERR_INVALID_ARG, "bad sorted block height %d", rows);
     const int64_t n = h->n_rows, nnz = h->nnz;
+    if ((int64_t)row_ptr.size() != n + 1 || row_start.empty() || row_start.front() != 0 ||
+        row_start.back() != n)
+        fail(SPMV_ERR_INVALID_ARG, "bad sorted block boundaries");
+    const int64_t blocks = (int64_t)row_start.size() - 1;
+    int32_t tallest = 0;
+    for (int64_t b = 0; b < blocks; ++b) {
+        const int32_t hgt = row_start[b + 1] - row_start[b];
+        if (hgt < 1 || hgt > max_rows) fail(SPMV_ERR_INVALID_ARG, "bad sorted block height %d", hgt);
+        tallest = std::max(tallest, hgt);
+    }
     const int col_bits = sorted_col_bits(h);
     P = SortedPart{};
     P.col_bits = col_bits;
-    P.rows = rows;
-    P.row16 = rows > sorted_packed_rows(h);
-    P.blocks = (int32_t)ceil_div(n, P.rows);
-    const int64_t blocks = P.blocks;
+    P.rows = tallest;
+    P.row16 = tallest > sorted_packed_rows(h);
+    P.blocks = (int32_t)blocks;
+    P.row_start = row_start;
     const size_t vs = dtype_size(h->dt);
+
+    // workgroup order: largest block first, so the last round is the small blocks
+    std::vector<int32_t> order(blocks);
+    for (int64_t b = 0; b < blocks; ++b) order[b] = (int32_t)b;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) {
+        return row_ptr[row_start[a + 1]] - row_ptr[row_start[a]] >
+               row_ptr[row_start[c + 1]] - row_ptr[row_start[c]];
+    });
+    P.blk_row.alloc((blocks + 1) * 4);
+    P.blk_order.alloc(std::max<int64_t>(blocks, 1) * 4);
+    SPMV_HIP(hipMemcpyAsync(P.blk_row.p, row_start.data(), (blocks + 1) * 4,
+                            hipMemcpyHostToDevice, s));
+    if (blocks > 0)
+        SPMV_HIP(hipMemcpyAsync(P.blk_order.p, order.data(), blocks * 4, hipMemcpyHostToDevice, s));
 
     DevBuf keys, perm, first, start;
     first.alloc((blocks + 1) * 4);
     start.alloc((blocks + 1) * 4);
-    sorted_blocks<<<grid_of_n(blocks + 1), kB, 0, s>>>(h->row_ptr.as<int32_t>(), h->n_rows, blocks,
-                                                       P.rows, first.as<int32_t>(),
-                                                       start.as<int32_t>());
+    sorted_blocks<<<grid_of_n(blocks + 1), kB, 0, s>>>(h->row_ptr.as<int32_t>(),
+                                                       P.blk_row.as<int32_t>(), blocks,
+                                                       first.as<int32_t>(), start.as<int32_t>());
     SPMV_CHECK_LAUNCH();
     exclusive_scan_i32(start.as<int32_t>(), start.as<int32_t>(), blocks + 1, s);
     int32_t total = 0;
     SPMV_HIP(hipMemcpyAsync(&total, start.as<int32_t>() + blocks, 4, hipMemcpyDeviceToHost, s));
-    SPMV_HIP(hipStreamSynchronize(s));
+    SPMV_HIP(hipStreamSynchronize(s));  // also keeps `order` alive until its copy is done
     P.stream = total;
     const int64_t cap = padded_count(total);
     P.idx.alloc(cap * 4);
@@ -474,8 +537,8 @@ void build_sorted_into(const spmv_matrix_s *h, int32_t rows, SortedPart &P, hipS
         keys.alloc(nnz * 8);
         perm.alloc(nnz * 4);
         sorted_keys<<<grid_of_n(nnz), kB, 0, s>>>(h->row.as<int32_t>(), h->col.as<int32_t>(), nnz,
-                                                  P.rows, col_bits, keys.as<uint64_t>(),
-                                                  perm.as<uint32_t>());
+                                                  P.blk_row.as<int32_t>(), P.blocks, col_bits,
+                                                  keys.as<uint64_t>(), perm.as<uint32_t>());
         SPMV_CHECK_LAUNCH();
         int bits = col_bits;
         while (bits < 64 && (uint64_t)(blocks - 1) >> (bits - col_bits)) ++bits;
@@ -483,13 +546,15 @@ void build_sorted_into(const spmv_matrix_s *h, int32_t rows, SortedPart &P, hipS
         if (h->dt == SPMV_F64)
             sorted_scatter<double><<<grid_of_n(nnz), kB, 0, s>>>(
                 perm.as<uint32_t>(), nnz, h->row.as<int32_t>(), h->col.as<int32_t>(),
-                h->val.as<double>(), first.as<int32_t>(), start.as<int32_t>(), P.rows, col_bits,
-                P.idx.as<int32_t>(), P.rows16.as<uint16_t>(), P.val.as<double>());
+                h->val.as<double>(), first.as<int32_t>(), start.as<int32_t>(),
+                P.blk_row.as<int32_t>(), P.blocks, col_bits, P.idx.as<int32_t>(),
+                P.rows16.as<uint16_t>(), P.val.as<double>());
         else
             sorted_scatter<float><<<grid_of_n(nnz), kB, 0, s>>>(
                 perm.as<uint32_t>(), nnz, h->row.as<int32_t>(), h->col.as<int32_t>(),
-                h->val.as<float>(), first.as<int32_t>(), start.as<int32_t>(), P.rows, col_bits,
-                P.idx.as<int32_t>(), P.rows16.as<uint16_t>(), P.val.as<float>());
+                h->val.as<float>(), first.as<int32_t>(), start.as<int32_t>(),
+                P.blk_row.as<int32_t>(), P.blocks, col_bits, P.idx.as<int32_t>(),
+                P.rows16.as<uint16_t>(), P.val.as<float>());
         SPMV_CHECK_LAUNCH();
     }
     P.blk_ptr = std::move(start);
