@@ -94,6 +94,8 @@ def kernel_symbols(fmt, info, dtype="float"):
         return [f"coo_tile_kernel<{dtype}, {b}, {l}, false>", f"coo_fixup<{dtype}, {b * l}, false>"]
     if info["kernel"] == "ell":
         return [f"ell_kernel<{dtype}, {b}, {l}, {u}>"]
+    if pp:  # HYB whose tail runs through the sorted-block COO kernel
+        return [f"ell_kernel<{dtype}, {b}, {l}, 4>", f"coo_sorted_kernel<{dtype}, {u}, "]
     return [f"ell_kernel<{dtype}, {b}, {l}, 4>", f"coo_tile_kernel<{dtype}, {b}, {u}, true>",
             f"coo_fixup<{dtype}, {b * u}, true>"]
 

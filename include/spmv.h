@@ -59,7 +59,12 @@ typedef enum spmv_kernel {
     SPMV_KERNEL_CSR_VECTOR = 1, /* `lanes` lanes of a wavefront per row           */
     SPMV_KERNEL_COO = 2,        /* nnz tiles, segmented reduction by row          */
     SPMV_KERNEL_ELL = 3,        /* `lanes` consecutive rows per thread            */
-    SPMV_KERNEL_HYB = 4,        /* ELL part (`lanes` rows/thread) + COO tail      */
+    SPMV_KERNEL_HYB = 4,        /* ELL part (`lanes` rows/thread) + COO tail; with
+                                   pipelined = 1 the tail is added by the sorted-
+                                   block COO kernel over a copy of the tail built
+                                   by spmv_set_variant / spmv_tune / spmv_time /
+                                   spmv_convert (its order of FP64 additions is not
+                                   fixed, as for SPMV_KERNEL_COO_SORTED)          */
     SPMV_KERNEL_COO_PANEL = 5,  /* COO entries of each row group (one per wave)
                                    streamed in column-panel order, so an XCD's x
                                    gathers stay in a window of x; needs a second

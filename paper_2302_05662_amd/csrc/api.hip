@@ -133,6 +133,7 @@ bool prepare_variant(spmv_matrix_s *h, spmv_format f, int32_t idx, hipStream_t s
     const bool sorted = variant_needs_sorted(f, idx) && !h->sorted.built;
     const bool split = variant_needs_split(f, idx) && !h->split.built;
     if (variant_needs_csr_blocks(f, idx) && !h->csr_blocks.built) build_csr_blocks(h, s);
+    if (variant_needs_hyb_sorted(f, idx) && !h->hyb_sorted.built) build_hyb_sorted(h, s);
     if (!panel && !sorted && !split) return true;
     try {
         if (panel) build_panel(h, s);
@@ -164,6 +165,8 @@ extern "C" spmv_status spmv_convert(spmv_handle h, spmv_format f, int32_t hyb_k,
         if (!h) fail(SPMV_ERR_INVALID_ARG, "NULL handle");
         if (!valid_format(f)) fail(SPMV_ERR_INVALID_ARG, "bad format %d", (int)f);
         convert(h, f, hyb_k, (hipStream_t)stream);
+        // a new HYB split drops the old tail's sorted copy: the current variant rebuilds it
+        if (f == SPMV_FMT_HYB) (void)prepare_variant(h, f, h->variant[f], (hipStream_t)stream);
     });
 }
 

@@ -282,7 +282,7 @@ void ensure_sorted(spmv_batch_s *b, hipStream_t s) {
         std::vector<int32_t> row_start;
         for (int64_t r = 0; r < n; r += rows) row_start.push_back((int32_t)r);
         row_start.push_back(n);
-        build_sorted_into(b->hs[m], b->row_ptr[m], row_start, parts[m], s);
+        build_sorted_into(b->hs[m], matrix_entries(b->hs[m]), b->row_ptr[m], row_start, parts[m], s);
     }
     b->sorted = std::move(parts);
     for (size_t m = 0; m < b->hs.size(); ++m) {

@@ -106,6 +106,7 @@ struct HybPart {
     int32_t K = 0, pitch = 0;
     int64_t nnz_tail = 0;
     DevBuf ell_col, ell_val, tail_row, tail_col, tail_val, partials;
+    DevBuf tail_ptr;  // tail_ptr[r]: tail entries of the rows before r (n_rows + 1)
 };
 
 // Column-panel ordered copy of the COO entries for the streaming COO kernel.
@@ -196,6 +197,7 @@ struct spmv_matrix_s {
     spmv::HybPart hyb;
     spmv::PanelPart panel;    // built on first use of a streaming COO variant
     spmv::SortedPart sorted;  // built on first use of a sorted-block COO variant
+    spmv::SortedPart hyb_sorted;  // the HYB tail's, built on first use of a sorted-tail HYB variant
     spmv::SplitPart split;    // built on first use of a column-split COO variant
     spmv::CsrBlocks csr_blocks;  // built on first use of a CSR stream variant
     spmv::RowStats stats;
@@ -232,10 +234,24 @@ int32_t sorted_packed_rows(const spmv_matrix_s *h);
 // block per CU as the height limit allows.
 std::vector<int32_t> sorted_balanced_rows(const std::vector<int32_t> &row_ptr, int32_t max_rows,
                                           int cus);
-// Build a sorted-block copy with the given block boundaries into P; row_ptr is a
-// host copy of the matrix's row pointers.
-void build_sorted_into(const spmv_matrix_s *h, const std::vector<int32_t> &row_ptr,
-                       const std::vector<int32_t> &row_start, SortedPart &P, hipStream_t s);
+// Entries a sorted-block copy is built from: the matrix's own (canonical COO and
+// row pointers) or its HYB tail, row-sorted, with row pointers over all rows.
+struct SortedEntries {
+    int64_t nnz;
+    const int32_t *row, *col, *row_ptr;
+    const void *val;
+};
+SortedEntries matrix_entries(const spmv_matrix_s *h);
+// Build a sorted-block copy of `src` (rows and columns of h) with the given block
+// boundaries into P; row_ptr is a host copy of src's row pointers.
+void build_sorted_into(const spmv_matrix_s *h, const SortedEntries &src,
+                       const std::vector<int32_t> &row_ptr, const std::vector<int32_t> &row_start,
+                       SortedPart &P, hipStream_t s);
+// Sorted-block copy of the HYB tail (h->hyb_sorted), for the HYB variants that
+// add the tail with the sorted-block kernel.
+void build_hyb_sorted(spmv_matrix_s *h, hipStream_t s);
+void hyb_sorted_tail(const spmv_matrix_s *h, int items, double alpha, const void *x, void *y,
+                     hipStream_t s);
 void build_split(spmv_matrix_s *h, hipStream_t s);  // NOT_APPLICABLE below two panels
 void sorted_spmv(const spmv_matrix_s *h, int items, double alpha, const void *x, double beta,
                  void *y, hipStream_t s);
@@ -246,6 +262,7 @@ bool variant_describe(spmv_format f, spmv_dtype dt, int32_t idx, spmv_variant_in
 int32_t default_variant(const spmv_matrix_s *h, spmv_format f);
 bool variant_needs_panel(spmv_format f, int32_t idx);
 bool variant_needs_sorted(spmv_format f, int32_t idx);
+bool variant_needs_hyb_sorted(spmv_format f, int32_t idx);
 bool variant_needs_split(spmv_format f, int32_t idx);
 bool variant_needs_csr_blocks(spmv_format f, int32_t idx);
 void build_csr_blocks(spmv_matrix_s *h, hipStream_t s);

@@ -154,8 +154,10 @@ void build_hyb(spmv_matrix_s *h, int32_t hyb_k, hipStream_t s) {
         SPMV_CHECK_LAUNCH();
     }
     SPMV_HIP(hipStreamSynchronize(s));
+    p.tail_ptr = std::move(off);  // the exclusive scan: the tail's row pointers
     p.built = true;
     h->hyb = std::move(p);
+    h->hyb_sorted = SortedPart{};  // a copy of the previous tail is stale
 }
 
 }  // namespace spmv

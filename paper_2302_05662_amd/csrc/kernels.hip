@@ -784,6 +784,17 @@ void hyb_launch(const Args &a) {
                                         h->hyb.partials.as<double>());
 }
 
+// HYB with its COO tail added by the sorted-block kernel (accumulate mode) after
+// the ELL part.
+template <class V, int RPT, int ITEMS>
+void hyb_sorted_launch(const Args &a) {
+    const spmv_matrix_s *h = a.h;
+    if (!h->hyb_sorted.built) fail(SPMV_ERR_NOT_CONVERTED, "sorted-block copy of the HYB tail not built");
+    ell_arrays_launch<V, RPT, 4>(h->n_rows, h->hyb.K, h->hyb.pitch, h->hyb.ell_col.as<int32_t>(),
+                                 h->hyb.ell_val.as<V>(), a);
+    hyb_sorted_tail(h, ITEMS, a.alpha, a.x, a.y, a.s);
+}
+
 #define V2(kind, blk, lanes, unr, fn) \
     Variant{{kind, blk, lanes, unr, 1, 0, 1}, fn<float>, fn<double>}
 #define V4(kind, blk, lanes, unr, fn) \
@@ -863,6 +874,9 @@ template <class V> void ell_2_8(const Args &a) { ell_launch<V, 2, 8>(a); }
 template <class V> void ell_4_4(const Args &a) { ell_launch<V, 4, 4>(a); }
 template <class V> void ell_4_8(const Args &a) { ell_launch<V, 4, 8>(a); }
 template <class V> void hyb_1_4(const Args &a) { hyb_launch<V, 1, 4>(a); }
+template <class V> void hyb_s1_8(const Args &a) { hyb_sorted_launch<V, 1, 8>(a); }
+template <class V> void hyb_s2_8(const Args &a) { hyb_sorted_launch<V, 2, 8>(a); }
+template <class V> void hyb_s2_16(const Args &a) { hyb_sorted_launch<V, 2, 16>(a); }
 template <class V> void hyb_1_8(const Args &a) { hyb_launch<V, 1, 8>(a); }
 template <class V> void hyb_2_4(const Args &a) { hyb_launch<V, 2, 4>(a); }
 template <class V> void hyb_2_8(const Args &a) { hyb_launch<V, 2, 8>(a); }
@@ -952,6 +966,10 @@ const std::vector<Variant> &table(spmv_format f) {
     static const std::vector<Variant> hyb = {
         VN(SPMV_KERNEL_HYB, 256, 1, 4, 1, hyb_1_4), VN(SPMV_KERNEL_HYB, 256, 1, 8, 1, hyb_1_8),
         VN(SPMV_KERNEL_HYB, 256, 2, 4, 2, hyb_2_4), VN(SPMV_KERNEL_HYB, 256, 2, 8, 2, hyb_2_8),
+        // pipelined = 1: the tail goes through the sorted-block COO kernel
+        Variant{{SPMV_KERNEL_HYB, 256, 1, 8, 1, 1, 1}, hyb_s1_8<float>, hyb_s1_8<double>},
+        Variant{{SPMV_KERNEL_HYB, 256, 2, 8, 2, 1, 1}, hyb_s2_8<float>, hyb_s2_8<double>},
+        Variant{{SPMV_KERNEL_HYB, 256, 2, 16, 2, 1, 1}, hyb_s2_16<float>, hyb_s2_16<double>},
     };
     static const std::vector<Variant> none;
     switch (f) {
@@ -1041,6 +1059,12 @@ void build_csr_blocks(spmv_matrix_s *h, hipStream_t s) {
     SPMV_HIP(hipStreamSynchronize(s));
     B.built = true;
     h->csr_blocks = std::move(B);
+}
+
+bool variant_needs_hyb_sorted(spmv_format f, int32_t idx) {
+    const auto &t = table(f);
+    return idx >= 0 && idx < (int32_t)t.size() && t[idx].info.kernel == SPMV_KERNEL_HYB &&
+           t[idx].info.pipelined == 1;
 }
 
 bool variant_needs_sorted(spmv_format f, int32_t idx) {

@@ -203,7 +203,9 @@ void launch_panel(const spmv_matrix_s *h, double alpha, const void *x, double be
 
 constexpr int kST = kSortedWaves * kWave;
 
-template <class V, int ITEMS, bool ROW16>
+// ACCUM: y += alpha * s for the rows the block has entries of (the HYB tail
+// after its ELL part), else y = alpha * s + beta * y for every row.
+template <class V, int ITEMS, bool ROW16, bool ACCUM>
 __global__ __launch_bounds__(kST) void coo_sorted_kernel(
     const int32_t *__restrict__ blk_row, const int32_t *__restrict__ blk_order, int32_t col_bits,
     const int32_t *__restrict__ blk_ptr, const int32_t *__restrict__ idx,
@@ -218,7 +220,13 @@ __global__ __launch_bounds__(kST) void coo_sorted_kernel(
     sorted_block_sum<V, ITEMS, kSortedWaves, ROW16>(idx, rows16, val, x, blk_ptr[b], blk_ptr[b + 1],
                                                     col_bits, last_load, s_y);
     __syncthreads();
-    for (int i = threadIdx.x; i < nr; i += kST) store_y(y, row0 + i, s_y[i], alpha, beta);
+    for (int i = threadIdx.x; i < nr; i += kST) {
+        if constexpr (ACCUM) {
+            if (s_y[i] != 0.0) y[row0 + i] = (V)((double)y[row0 + i] + (double)alpha * s_y[i]);
+        } else {
+            store_y(y, row0 + i, s_y[i], alpha, beta);
+        }
+    }
 }
 
 // Block holding row r: the last b with blk_row[b] <= r (blocks are never empty).
@@ -291,18 +299,18 @@ __global__ void sorted_scatter(const uint32_t *__restrict__ perm, int64_t nnz,
     }
 }
 
-template <class V, int ITEMS>
-void launch_sorted(const spmv_matrix_s *h, double alpha, const void *x, double beta, void *y,
+template <class V, int ITEMS, bool ACCUM = false>
+void launch_sorted(const SortedPart &P, double alpha, const void *x, double beta, void *y,
                    hipStream_t s) {
-    const SortedPart &P = h->sorted;
+    if (P.blocks == 0) return;
     const int64_t cap = padded_count(P.stream);
     if (P.row16)
-        coo_sorted_kernel<V, ITEMS, true><<<P.blocks, kST, 0, s>>>(
+        coo_sorted_kernel<V, ITEMS, true, ACCUM><<<P.blocks, kST, 0, s>>>(
             P.blk_row.as<int32_t>(), P.blk_order.as<int32_t>(), P.col_bits,
             P.blk_ptr.as<int32_t>(), P.idx.as<int32_t>(), P.rows16.as<uint16_t>(), P.val.as<V>(),
             cap - 4, (const V *)x, (V)alpha, (V)beta, (V *)y);
     else
-        coo_sorted_kernel<V, ITEMS, false><<<P.blocks, kST, 0, s>>>(
+        coo_sorted_kernel<V, ITEMS, false, ACCUM><<<P.blocks, kST, 0, s>>>(
             P.blk_row.as<int32_t>(), P.blk_order.as<int32_t>(), P.col_bits,
             P.blk_ptr.as<int32_t>(), P.idx.as<int32_t>(), nullptr, P.val.as<V>(), cap - 4,
             (const V *)x, (V)alpha, (V)beta, (V *)y);
@@ -471,14 +479,38 @@ void build_sorted(spmv_matrix_s *h, hipStream_t s) {
     // slowest), as few blocks as possible, in whole rounds of one block per CU
     const std::vector<int32_t> row_start = sorted_balanced_rows(rp, kSortedRowsMax, cus);
     SortedPart P;
-    build_sorted_into(h, rp, row_start, P, s);
+    build_sorted_into(h, matrix_entries(h), rp, row_start, P, s);
     h->sorted = std::move(P);
 }
 
-void build_sorted_into(const spmv_matrix_s *h, const std::vector<int32_t> &row_ptr,
-                       const std::vector<int32_t> &row_start, SortedPart &P, hipStream_t s) {
+SortedEntries matrix_entries(const spmv_matrix_s *h) {
+    return SortedEntries{h->nnz, h->row.as<int32_t>(), h->col.as<int32_t>(),
+                         h->row_ptr.as<int32_t>(), h->val.p};
+}
+
+void build_hyb_sorted(spmv_matrix_s *h, hipStream_t s) {
+    if (h->hyb_sorted.built) return;
+    if (!h->hyb.built) fail(SPMV_ERR_NOT_CONVERTED, "HYB not converted");
+    (void)sorted_max_rows(h);
+    int cus = 0;
+    SPMV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
+    std::vector<int32_t> rp(h->n_rows + 1);
+    SPMV_HIP(hipMemcpyAsync(rp.data(), h->hyb.tail_ptr.p, rp.size() * 4, hipMemcpyDeviceToHost, s));
+    SPMV_HIP(hipStreamSynchronize(s));
+    const std::vector<int32_t> row_start = sorted_balanced_rows(rp, kSortedRowsMax, cus);
+    const SortedEntries tail{h->hyb.nnz_tail, h->hyb.tail_row.as<int32_t>(),
+                             h->hyb.tail_col.as<int32_t>(), h->hyb.tail_ptr.as<int32_t>(),
+                             h->hyb.tail_val.p};
+    SortedPart P;
+    build_sorted_into(h, tail, rp, row_start, P, s);
+    h->hyb_sorted = std::move(P);
+}
+
+void build_sorted_into(const spmv_matrix_s *h, const SortedEntries &src,
+                       const std::vector<int32_t> &row_ptr, const std::vector<int32_t> &row_start,
+                       SortedPart &P, hipStream_t s) {
     const int32_t max_rows = sorted_max_rows(h);
-    const int64_t n = h->n_rows, nnz = h->nnz;
+    const int64_t n = h->n_rows, nnz = src.nnz;
     if ((int64_t)row_ptr.size() != n + 1 || row_start.empty() || row_start.front() != 0 ||
         row_start.back() != n)
         fail(SPMV_ERR_INVALID_ARG, "bad sorted block boundaries");
@@ -515,8 +547,7 @@ void build_sorted_into(const spmv_matrix_s *h, const std::vector<int32_t> &row_p
     DevBuf keys, perm, first, start;
     first.alloc((blocks + 1) * 4);
     start.alloc((blocks + 1) * 4);
-    sorted_blocks<<<grid_of_n(blocks + 1), kB, 0, s>>>(h->row_ptr.as<int32_t>(),
-                                                       P.blk_row.as<int32_t>(), blocks,
+    sorted_blocks<<<grid_of_n(blocks + 1), kB, 0, s>>>(src.row_ptr, P.blk_row.as<int32_t>(), blocks,
                                                        first.as<int32_t>(), start.as<int32_t>());
     SPMV_CHECK_LAUNCH();
     exclusive_scan_i32(start.as<int32_t>(), start.as<int32_t>(), blocks + 1, s);
@@ -536,23 +567,23 @@ void build_sorted_into(const spmv_matrix_s *h, const std::vector<int32_t> &row_p
     if (nnz > 0) {
         keys.alloc(nnz * 8);
         perm.alloc(nnz * 4);
-        sorted_keys<<<grid_of_n(nnz), kB, 0, s>>>(h->row.as<int32_t>(), h->col.as<int32_t>(), nnz,
-                                                  P.blk_row.as<int32_t>(), P.blocks, col_bits,
-                                                  keys.as<uint64_t>(), perm.as<uint32_t>());
+        sorted_keys<<<grid_of_n(nnz), kB, 0, s>>>(src.row, src.col, nnz, P.blk_row.as<int32_t>(),
+                                                  P.blocks, col_bits, keys.as<uint64_t>(),
+                                                  perm.as<uint32_t>());
         SPMV_CHECK_LAUNCH();
         int bits = col_bits;
         while (bits < 64 && (uint64_t)(blocks - 1) >> (bits - col_bits)) ++bits;
         radix_sort_pairs(keys, perm, nnz, bits, s);
         if (h->dt == SPMV_F64)
             sorted_scatter<double><<<grid_of_n(nnz), kB, 0, s>>>(
-                perm.as<uint32_t>(), nnz, h->row.as<int32_t>(), h->col.as<int32_t>(),
-                h->val.as<double>(), first.as<int32_t>(), start.as<int32_t>(),
+                perm.as<uint32_t>(), nnz, src.row, src.col, (const double *)src.val,
+                first.as<int32_t>(), start.as<int32_t>(),
                 P.blk_row.as<int32_t>(), P.blocks, col_bits, P.idx.as<int32_t>(),
                 P.rows16.as<uint16_t>(), P.val.as<double>());
         else
             sorted_scatter<float><<<grid_of_n(nnz), kB, 0, s>>>(
-                perm.as<uint32_t>(), nnz, h->row.as<int32_t>(), h->col.as<int32_t>(),
-                h->val.as<float>(), first.as<int32_t>(), start.as<int32_t>(),
+                perm.as<uint32_t>(), nnz, src.row, src.col, (const float *)src.val,
+                first.as<int32_t>(), start.as<int32_t>(),
                 P.blk_row.as<int32_t>(), P.blocks, col_bits, P.idx.as<int32_t>(),
                 P.rows16.as<uint16_t>(), P.val.as<float>());
         SPMV_CHECK_LAUNCH();
@@ -566,14 +597,29 @@ void sorted_spmv(const spmv_matrix_s *h, int items, double alpha, const void *x,
                  void *y, hipStream_t s) {
     if (!h->sorted.built) fail(SPMV_ERR_NOT_CONVERTED, "sorted-block COO layout not built");
     if (h->n_rows == 0) return;
+    const SortedPart &P = h->sorted;
     if (h->dt == SPMV_F64) {
-        if (items == 4) launch_sorted<double, 4>(h, alpha, x, beta, y, s);
-        else if (items == 8) launch_sorted<double, 8>(h, alpha, x, beta, y, s);
-        else launch_sorted<double, 16>(h, alpha, x, beta, y, s);
+        if (items == 4) launch_sorted<double, 4>(P, alpha, x, beta, y, s);
+        else if (items == 8) launch_sorted<double, 8>(P, alpha, x, beta, y, s);
+        else launch_sorted<double, 16>(P, alpha, x, beta, y, s);
     } else {
-        if (items == 4) launch_sorted<float, 4>(h, alpha, x, beta, y, s);
-        else if (items == 8) launch_sorted<float, 8>(h, alpha, x, beta, y, s);
-        else launch_sorted<float, 16>(h, alpha, x, beta, y, s);
+        if (items == 4) launch_sorted<float, 4>(P, alpha, x, beta, y, s);
+        else if (items == 8) launch_sorted<float, 8>(P, alpha, x, beta, y, s);
+        else launch_sorted<float, 16>(P, alpha, x, beta, y, s);
+    }
+}
+
+void hyb_sorted_tail(const spmv_matrix_s *h, int items, double alpha, const void *x, void *y,
+                     hipStream_t s) {
+    if (!h->hyb_sorted.built) fail(SPMV_ERR_NOT_CONVERTED, "sorted-block copy of the HYB tail not built");
+    if (h->n_rows == 0 || h->hyb.nnz_tail == 0) return;
+    const SortedPart &P = h->hyb_sorted;
+    if (h->dt == SPMV_F64) {
+        if (items == 8) launch_sorted<double, 8, true>(P, alpha, x, 0.0, y, s);
+        else launch_sorted<double, 16, true>(P, alpha, x, 0.0, y, s);
+    } else {
+        if (items == 8) launch_sorted<float, 8, true>(P, alpha, x, 0.0, y, s);
+        else launch_sorted<float, 16, true>(P, alpha, x, 0.0, y, s);
     }
 }
 

@@ -119,6 +119,10 @@ double tune_format(spmv_matrix_s *h, spmv_format f, const void *x, void *y, int3
         if (h->sorted.built && !variant_needs_sorted(f, bi)) h->sorted = SortedPart{};
         if (h->split.built && !variant_needs_split(f, bi)) h->split = SplitPart{};
     }
+    if (f == SPMV_FMT_HYB && h->hyb_sorted.built && !variant_needs_hyb_sorted(f, bi)) {
+        SPMV_HIP(hipStreamSynchronize(s));
+        h->hyb_sorted = SortedPart{};
+    }
     if (best_idx) *best_idx = bi;
     return best;
 }

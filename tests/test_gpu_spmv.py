@@ -122,8 +122,10 @@ def test_beta_zero_ignores_nan_and_runs_are_deterministic(dtype):
             S.spmv_run(h, fmt, 1.0, xd, 0.0, y1)
             S.spmv_run(h, fmt, 1.0, xd, 0.0, y2)
             a, b = y1.cpu().numpy(), y2.cpu().numpy()
-            # the sorted-block COO kernel adds with LDS atomics in no fixed order
-            if S.spmv_variant_describe(fmt, h.dtype_code, var)["kernel"] != "coo_sorted":
+            # the sorted-block COO kernel (also the tail of the HYB variants with
+            # pipelined = 1) adds with LDS atomics in no fixed order
+            d = S.spmv_variant_describe(fmt, h.dtype_code, var)
+            if d["kernel"] != "coo_sorted" and not (d["kernel"] == "hyb" and d["pipelined"] == 1):
                 assert a.tobytes() == b.tobytes()
             assert OS.max_row_error(a, y_ref, den) <= C.TOL[dtype]
 
@@ -346,3 +348,35 @@ def test_csr_stream_rows_at_the_stage_size(dtype):
                 first = got.tobytes()
             assert got.tobytes() == first
         assert OS.max_row_error(got, y_ref, den) <= C.TOL[dtype], var
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_hyb_sorted_tail_follows_a_new_split(dtype):
+    """HYB variants that add the tail with the sorted-block kernel: right for several ELL
+    widths, and a new spmv_convert of HYB (another width, so another tail) keeps the chosen
+    variant runnable and right."""
+    m = synth.power_law(20000, 71, cap=5000, value_dist="uniform")
+    print(f"[spmv hyb sorted tail] nnz={m.nnz} {dtype.__name__}", flush=True)
+    v = m.values(dtype)
+    x = synth.uniform_vector(m.n_cols, dtype, [71, 3])
+    y0 = synth.uniform_vector(m.n_rows, dtype, [71, 4])
+    a, b = 1.5, -0.5
+    c = OF.canonicalize(m.n_rows, m.n_cols, m.row, m.col, v)
+    y_ref = OS.spmv_csr(c["row_ptr"], c["col"], c["val"], x, dtype(a), dtype(b), y0)
+    den = OS.row_denominator(c["row_ptr"], c["col"], c["val"], x, dtype(a), dtype(b), y0)
+    h = S.spmv_create(m.n_rows, m.n_cols, m.row, m.col, v)
+    xd = torch.from_numpy(x).cuda()
+    tails = [i for i in range(S.spmv_variant_count(S.SPMV_FMT_HYB, h.dtype_code))
+             if S.spmv_variant_describe(S.SPMV_FMT_HYB, h.dtype_code, i)["pipelined"] == 1]
+    assert tails
+    for k in (0, 1, 3, 8):
+        S.spmv_convert(h, S.SPMV_FMT_HYB, hyb_k=k)
+        for var in tails:
+            S.spmv_set_variant(h, S.SPMV_FMT_HYB, var)
+            yd = torch.from_numpy(y0.copy()).cuda()
+            S.spmv_run(h, S.SPMV_FMT_HYB, a, xd, b, yd)
+            assert OS.max_row_error(yd.cpu().numpy(), y_ref, den) <= C.TOL[dtype], (k, var)
+    S.spmv_convert(h, S.SPMV_FMT_HYB, hyb_k=2)  # the last variant stays set
+    yd = torch.from_numpy(y0.copy()).cuda()
+    S.spmv_run(h, S.SPMV_FMT_HYB, a, xd, b, yd)
+    assert OS.max_row_error(yd.cpu().numpy(), y_ref, den) <= C.TOL[dtype]
