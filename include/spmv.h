@@ -248,7 +248,8 @@ spmv_status spmv_select_format(spmv_handle h, spmv_select_mode m, spmv_format *o
 
 typedef struct spmv_batch_config {
     int32_t block;           /* workgroup size (256)                                 */
-    int32_t unroll;          /* 16-byte loads in flight per lane (1 or 2)            */
+    int32_t unroll;          /* 16-byte loads in flight per lane (1 or 2; 4 also for
+                                tiling 2)                                            */
     int32_t passes_per_tile; /* a tile = this many passes of block/lanes rows        */
     int32_t blocks_per_cu;   /* persistent workgroups per compute unit               */
     int32_t lanes_divisor;   /* lanes per row = smallest power of two >=
@@ -260,7 +261,7 @@ typedef struct spmv_batch_config {
                                 their own reduced by the whole workgroup); 2: the
                                 batch's sorted-block COO copy of every matrix, one
                                 block (<= 4096 rows, entries sorted by column) per
-                                1024-thread tile, largest first, unroll 1/2 = 4/8
+                                1024-thread tile, largest first, unroll 1/2/4 = 4/8/16
                                 entries per lane; the order of the FP64 row sums is
                                 not fixed (see SPMV_KERNEL_COO_SORTED); needs a
                                 second copy of every matrix's entries               */
@@ -296,9 +297,9 @@ spmv_status spmv_batch_update(spmv_batch b, const void *const *xs, void *const *
 spmv_status spmv_batch_get_config(spmv_batch b, spmv_batch_config *out, int32_t *lanes);
 
 /* Rebuild the batch's graph with the setting *cfg (block, total_tiles, grid and
- * tuned_ms are ignored): unroll 1 or 2, passes_per_tile >= 1, blocks_per_cu
- * >= 1, lanes_divisor >= 1, tiling 0, 1 or 2. Errors: INVALID_ARG, NOT_APPLICABLE
- * (tiling 2 on a matrix whose columns leave no bits for rows), OOM, HIP.
+ * tuned_ms are ignored): unroll 1 or 2 (or 4 with tiling 2), passes_per_tile >= 1,
+ * blocks_per_cu >= 1, lanes_divisor >= 1, tiling 0, 1 or 2. Errors: INVALID_ARG,
+ * NOT_APPLICABLE (tiling 2 on a matrix of more than 2^30 entries), OOM, HIP.
  * Synchronises `stream`. */
 spmv_status spmv_batch_set_config(spmv_batch b, const spmv_batch_config *cfg, void *stream);
 

@@ -170,8 +170,13 @@ using BatchKernel = void (*)(const BatchDesc *, const BatchTile *, int32_t, int3
 
 BatchKernel kernel_for(spmv_dtype dt, int unroll, int tiling) {
     if (tiling == 2) {
-        if (dt == SPMV_F64) return unroll == 2 ? batch_sorted_kernel<double, 8> : batch_sorted_kernel<double, 4>;
-        return unroll == 2 ? batch_sorted_kernel<float, 8> : batch_sorted_kernel<float, 4>;
+        if (dt == SPMV_F64)
+            return unroll == 4   ? batch_sorted_kernel<double, 16>
+                   : unroll == 2 ? batch_sorted_kernel<double, 8>
+                                 : batch_sorted_kernel<double, 4>;
+        return unroll == 4   ? batch_sorted_kernel<float, 16>
+               : unroll == 2 ? batch_sorted_kernel<float, 8>
+                             : batch_sorted_kernel<float, 4>;
     }
     if (dt == SPMV_F64) return unroll == 2 ? batch_kernel<double, 2> : batch_kernel<double, 1>;
     return unroll == 2 ? batch_kernel<float, 2> : batch_kernel<float, 1>;
@@ -479,7 +484,7 @@ extern "C" spmv_status spmv_batch_create(spmv_batch *out, const spmv_handle *hs,
             }
         }
         if (sorted_ok)
-            for (int unroll : {1, 2})
+            for (int unroll : {1, 2, 4})
                 for (int bpc : {1, 2}) {
                     spmv_batch_config c{};
                     c.tiling = 2;
@@ -539,8 +544,10 @@ extern "C" spmv_status spmv_batch_set_config(spmv_batch b, const spmv_batch_conf
                                              void *stream) {
     return guard([&] {
         if (!b || !cfg) fail(SPMV_ERR_INVALID_ARG, "NULL argument");
-        if ((cfg->unroll != 1 && cfg->unroll != 2) || cfg->passes_per_tile < 1 ||
-            cfg->blocks_per_cu < 1 || cfg->lanes_divisor < 1 || cfg->tiling < 0 || cfg->tiling > 2)
+        const bool unroll_ok = cfg->unroll == 1 || cfg->unroll == 2 ||
+                               (cfg->unroll == 4 && cfg->tiling == 2);
+        if (!unroll_ok || cfg->passes_per_tile < 1 || cfg->blocks_per_cu < 1 ||
+            cfg->lanes_divisor < 1 || cfg->tiling < 0 || cfg->tiling > 2)
             fail(SPMV_ERR_INVALID_ARG, "bad batch setting");
         build_graph(b, *cfg, (hipStream_t)stream);
     });

@@ -67,7 +67,8 @@ def test_batch_matches_oracle_and_single_launches(dtype, tune):
     tol = 1e-5 if dtype == np.float32 else 1e-12
     settings = [None, dict(tiling=1, unroll=2, passes_per_tile=1, lanes_divisor=2),
                 dict(tiling=0, unroll=1), dict(tiling=0, unroll=2, passes_per_tile=16),
-                dict(tiling=2, unroll=1, blocks_per_cu=1), dict(tiling=2, unroll=2, blocks_per_cu=2)]
+                dict(tiling=2, unroll=1, blocks_per_cu=1), dict(tiling=2, unroll=2, blocks_per_cu=2),
+                dict(tiling=2, unroll=4, blocks_per_cu=1)]
     for setting in settings:
         if setting is not None:
             S.spmv_batch_set_config(b, **setting)
@@ -122,6 +123,9 @@ def test_batch_argument_errors():
     b = S.spmv_batch_create(hs[:3], xs[:3], ys[:3], tune=False)
     with pytest.raises(S.SpmvError) as e:
         S.spmv_batch_update(b, xs=[ys[0], xs[1], xs[2]], ys=[ys[0], ys[1], ys[2]])
+    assert e.value.status == "INVALID_ARG"
+    with pytest.raises(S.SpmvError) as e:  # 16 entries per lane only with the sorted tiling
+        S.spmv_batch_set_config(b, tiling=0, unroll=4)
     assert e.value.status == "INVALID_ARG"
     S.spmv_batch_run(b)  # still valid with the old pointers
     torch.cuda.synchronize()
