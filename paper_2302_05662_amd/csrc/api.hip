@@ -129,16 +129,12 @@ spmv_format select_rule(const float f[12], float votes[4]) {
 }  // namespace
 
 bool prepare_variant(spmv_matrix_s *h, spmv_format f, int32_t idx, hipStream_t s) {
-    const bool panel = variant_needs_panel(f, idx) && !h->panel.built;
-    const bool sorted = variant_needs_sorted(f, idx) && !h->sorted.built;
-    const bool split = variant_needs_split(f, idx) && !h->split.built;
-    if (variant_needs_csr_blocks(f, idx) && !h->csr_blocks.built) build_csr_blocks(h, s);
-    if (variant_needs_hyb_sorted(f, idx) && !h->hyb_sorted.built) build_hyb_sorted(h, s);
-    if (!panel && !sorted && !split) return true;
     try {
-        if (panel) build_panel(h, s);
-        if (sorted) build_sorted(h, s);
-        if (split) build_split(h, s);
+        if (variant_needs_panel(f, idx) && !h->panel.built) build_panel(h, s);
+        if (variant_needs_sorted(f, idx) && !h->sorted.built) build_sorted(h, s);
+        if (variant_needs_split(f, idx) && !h->split.built) build_split(h, s);
+        if (variant_needs_csr_blocks(f, idx) && !h->csr_blocks.built) build_csr_blocks(h, s);
+        if (variant_needs_hyb_sorted(f, idx) && !h->hyb_sorted.built) build_hyb_sorted(h, s);
     } catch (const Error &e) {
         if (e.status != SPMV_ERR_NOT_APPLICABLE) throw;
         clear_error();

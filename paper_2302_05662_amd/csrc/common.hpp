@@ -266,8 +266,10 @@ bool variant_needs_hyb_sorted(spmv_format f, int32_t idx);
 bool variant_needs_split(spmv_format f, int32_t idx);
 bool variant_needs_csr_blocks(spmv_format f, int32_t idx);
 void build_csr_blocks(spmv_matrix_s *h, hipStream_t s);
-// Make variant idx of f runnable: builds the panel layout for a panel variant.
-// Returns false when that layout is not applicable to the matrix.
+// Make variant idx of f runnable: builds the reordered copy or block table the
+// variant reads (streaming, sorted-block or column-split COO copy, CSR stream
+// row blocks, sorted copy of the HYB tail) unless it is built. Returns false when
+// that layout is not applicable to the matrix.
 bool prepare_variant(spmv_matrix_s *h, spmv_format f, int32_t idx, hipStream_t s);
 void launch_spmv(const spmv_matrix_s *h, spmv_format f, int32_t variant, double alpha,
                  const void *x, double beta, void *y, hipStream_t s);
