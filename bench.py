@@ -521,9 +521,10 @@ def main():
         if entry["variant"].get(1, -1) >= 0 and \
                 S.spmv_variant_describe(1, S.SPMV_F32, entry["variant"][1])["kernel"] in (
                     "coo_panel", "coo_sorted"):
-            # the reordered COO copies pack row and column in one index: 8 bytes per FP32
-            # entry plus one pointer per row group or block, priced like CSR (a small
-            # underestimate: each group's or block's stream is padded to 4 entries)
+            # the reordered COO copies keep one index per entry (row packed with the column,
+            # or the column with a 16-bit row beside it in tall sorted blocks) plus one
+            # pointer per row group or block, priced like CSR (an underestimate: the
+            # padding and the 16-bit rows are not counted)
             entry["bytes"][1] = format_bytes(0, m.n_rows, m.n_cols, m.nnz, 4)
         for fmt in range(4):
             entry["variant"].setdefault(fmt, -1)
@@ -578,6 +579,17 @@ def main():
     def new_events(n):
         return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                 for _ in range(n)]
+
+    # The chosen plan, each SpMV timed alone after a cache scrub: median, mean and p95
+    # over 20 runs per matrix, summed over the matrices (before the timed steps, so
+    # the timed launches stay the run's last SpMV dispatches).
+    cold = np.array([S.spmv_time(e["h"], e["fmt"], e["xd"], e["y"], variant=e["variant"][e["fmt"]],
+                                 warmup=1, reps=20, flush=True) for e in mats])  # ms, [30, 20]
+    useful_all = sum(e["useful_bytes"] for e in mats)
+    cold_plan = {"reps": 20, "median_ms": round(float(np.median(cold, axis=1).sum()), 4),
+                 "mean_ms": round(float(cold.mean(axis=1).sum()), 4),
+                 "p95_ms": round(float(np.percentile(cold, 95, axis=1).sum()), 4)}
+    cold_plan["useful_gbps_median"] = round(useful_all / (cold_plan["median_ms"] * 1e-3) / 1e9, 1)
 
     # Warmup steps carry a pair of events on every launch: they give the kernel time per
     # step and pick the roofline kernel, the (format, variant) group with the largest
@@ -708,6 +720,7 @@ def main():
         "cpu_baseline": cpu,
         "copy_calibration_mib": args.copy_calibration,
         "per_format_tuned_cold": per_format,
+        "cold_plan": cold_plan,
         "selected_formats": chosen,
         "setup_s": round(setup_s, 1),
         "setup_rates": setup_rates,
