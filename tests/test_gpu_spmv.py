@@ -369,6 +369,9 @@ def test_hyb_sorted_tail_follows_a_new_split(dtype):
     tails = [i for i in range(S.spmv_variant_count(S.SPMV_FMT_HYB, h.dtype_code))
              if S.spmv_variant_describe(S.SPMV_FMT_HYB, h.dtype_code, i)["pipelined"] == 1]
     assert tails
+    with pytest.raises(S.SpmvError) as e:  # the tail's copy needs a HYB split first
+        S.spmv_set_variant(h, S.SPMV_FMT_HYB, tails[0])
+    assert e.value.status == "NOT_CONVERTED"
     for k in (0, 1, 3, 8):
         S.spmv_convert(h, S.SPMV_FMT_HYB, hyb_k=k)
         for var in tails:
