@@ -17,7 +17,9 @@
  *   - Every function returns a status and never throws or aborts across the
  *     ABI. spmv_last_error() gives a message for the calling thread.
  *   - Handles are owned by the library; spmv_create copies its inputs. A
- *     handle is not thread-safe: calls on one handle must not overlap.
+ *     handle is not thread-safe: calls on one handle must not overlap, and
+ *     runs of one handle enqueued on different streams must not execute at
+ *     the same time (the COO kernels keep per-tile carries in the handle).
  *   - The current device at spmv_create is the handle's device; later calls
  *     on the handle must run with that device current.
  */
