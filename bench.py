@@ -616,28 +616,46 @@ def main():
     # launches first, back to back, bracketed by one pair of events (per-launch events
     # would add their own dispatch gaps), then the others; all K steps are enqueued
     # without waiting, so launch overhead overlaps the kernels.
-    order = sorted(range(len(mats)), key=lambda i: (i not in members, i))
+    # Inside the group the launches are ordered by kernel instance, with one more event
+    # at each change of instance, which gives each instance its own achieved rate.
+    def instance(e):
+        info = S.spmv_variant_describe(e["fmt"], S.SPMV_F32, e["variant"][e["fmt"]])
+        return kernel_symbols(e["fmt"], info)[0]
+
+    order = sorted(range(len(mats)),
+                   key=lambda i: (i not in members, instance(mats[i]) if i in members else "", i))
     mats[:] = [mats[i] for i in order]
     n_dom = len(members)
+    inst = [instance(mats[i]) for i in range(n_dom)]
+    bounds = [0] + [i for i in range(1, n_dom) if inst[i] != inst[i - 1]] + [n_dom]
 
-    def timed_step(pair):
+    def timed_step(evl):
         for i, e in enumerate(mats):
             if i == 0:
-                pair[0].record(stream)
+                evl[0].record(stream)
             S.spmv_run(e["h"], e["fmt"], 1.0, e["xd"], 0.0, e["y"])
-            if i == n_dom - 1:
-                pair[1].record(stream)
+            if i + 1 in bounds[1:]:
+                evl[bounds.index(i + 1)].record(stream)
 
-    evs = [new_events(1)[0] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in bounds] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         timed_step(evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    dom["ms"] = sum(a.elapsed_time(b) for a, b in evs)
+    dom["ms"] = sum(evl[0].elapsed_time(evl[-1]) for evl in evs)
     dom["launches"] = n_dom * args.steps
     dom["bytes"] = args.steps * sum(e["bytes"][e["fmt"]] for e in mats[:n_dom])
+    instances = []
+    for j in range(len(bounds) - 1):
+        a, b = bounds[j], bounds[j + 1]
+        ms = sum(evl[j].elapsed_time(evl[j + 1]) for evl in evs)
+        nb = args.steps * sum(e["bytes"][e["fmt"]] for e in mats[a:b])
+        gbps = nb / (ms * 1e-3) / 1e9
+        instances.append({"kernel_symbol": inst[a], "launches": (b - a) * args.steps,
+                          "avg_launch_us": round(ms * 1e3 / ((b - a) * args.steps), 3),
+                          "achieved": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4)})
     if args.copy_calibration:
         src = torch.zeros(args.copy_calibration * 2**18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -716,6 +734,7 @@ def main():
             "launches": dom["launches"],
             "avg_launch_us": round(dom["ms"] * 1e3 / dom["launches"], 3),
             "bytes_per_launch": round(dom["bytes"] / dom["launches"], 1),
+            "instances": instances,
         },
         "cpu_baseline": cpu,
         "copy_calibration_mib": args.copy_calibration,
