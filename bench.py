@@ -452,8 +452,9 @@ def main():
         counter_summary(*args.counter_summary)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(the multi-GPU design is described, not run)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the library "
+              "runs each SpMV on one GPU, and sharding rows across GPUs is designed, not "
+              "implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
