@@ -276,18 +276,24 @@ typedef struct spmv_batch_config {
  * device, with y_i = alpha_i * A_i * x_i + beta_i * y_i for each i.
  *   hs: host array of handles (borrowed: they must outlive the batch);
  *   xs, ys: host arrays of device pointers (x_i: n_cols_i values, y_i:
- *   n_rows_i values, not overlapping); alphas, betas: host arrays or NULL (1
- *   and 0). If tune != 0 every setting of a small grid (unroll, tile size,
+ *   n_rows_i values); no y_i may overlap any x_j or any other y_j (the x_i
+ *   may be shared); alphas, betas: host arrays or NULL (1 and 0). If tune != 0 every setting of a small grid (unroll, tile size,
  *   workgroups per CU, lanes rule) is captured and timed and the fastest kept.
  * Errors: INVALID_ARG, OOM, HIP. Synchronises `stream`. */
 spmv_status spmv_batch_create(spmv_batch *out, const spmv_handle *hs, int32_t count,
                               const void *const *xs, void *const *ys, const double *alphas,
                               const double *betas, int tune, void *stream);
 
-/* One graph launch computing every product of the batch. Asynchronous.
+/* One graph launch computing y_i = alpha_i * A_i * x_i + beta_i * y_i for every
+ * matrix of the batch. Asynchronous on `stream`.
+ *   alphas, betas: host double[count]; xs, ys: host arrays of count device
+ *   pointers. Any of them may be NULL to keep the values the batch holds (from
+ *   spmv_batch_create or an earlier run or update); given ones replace them for
+ *   this and later runs (the descriptor upload is enqueued before the launch).
  * Runs on one stream must not overlap (they share the tile counter).
- * Errors: INVALID_ARG, HIP. */
-spmv_status spmv_batch_run(spmv_batch b, void *stream);
+ * Errors: INVALID_ARG (as spmv_batch_create; the batch is left unchanged), HIP. */
+spmv_status spmv_batch_run(spmv_batch b, const double *alphas, const void *const *xs,
+                           const double *betas, void *const *ys, void *stream);
 
 /* Re-point the batch (any array may be NULL to keep it); enqueued on `stream`
  * before later runs. Errors: INVALID_ARG (the batch is left unchanged), HIP. */

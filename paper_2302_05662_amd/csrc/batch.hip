@@ -380,11 +380,30 @@ void set_io(spmv_batch_s *b, const void *const *xs, void *const *ys, const doubl
         if (betas) d.beta = betas[i];
         if ((h->n_cols > 0 && !d.x) || (h->n_rows > 0 && !d.y))
             fail(SPMV_ERR_INVALID_ARG, "matrix %zu: NULL x or y", i);
-        if (d.x && d.y && h->n_rows > 0 && h->n_cols > 0) {
-            const char *xb = (const char *)d.x, *xe = xb + (size_t)h->n_cols * vs;
-            const char *yb = (const char *)d.y, *ye = yb + (size_t)h->n_rows * vs;
-            if (xb < ye && yb < xe) fail(SPMV_ERR_INVALID_ARG, "matrix %zu: x and y overlap", i);
-        }
+    }
+    // One launch computes every product, so no y may share a byte with any x or
+    // any other y (the x vectors may be shared: they are only read).
+    struct Range {
+        uintptr_t b, e;
+        size_t i;
+    };
+    std::vector<Range> yr, xr;
+    for (size_t i = 0; i < b->hs.size(); ++i) {
+        const spmv_matrix_s *h = b->hs[i];
+        const BatchDesc &d = b->desc[i];
+        if (h->n_rows > 0) yr.push_back({(uintptr_t)d.y, (uintptr_t)d.y + (size_t)h->n_rows * vs, i});
+        if (h->n_cols > 0) xr.push_back({(uintptr_t)d.x, (uintptr_t)d.x + (size_t)h->n_cols * vs, i});
+    }
+    std::sort(yr.begin(), yr.end(), [](const Range &a, const Range &c) { return a.b < c.b; });
+    for (size_t k = 1; k < yr.size(); ++k)
+        if (yr[k].b < yr[k - 1].e)
+            fail(SPMV_ERR_INVALID_ARG, "y of matrices %zu and %zu overlap", yr[k - 1].i, yr[k].i);
+    for (const Range &x : xr) {
+        // the y ranges are disjoint and sorted: only the last one starting before x ends can meet it
+        auto it = std::lower_bound(yr.begin(), yr.end(), x.e,
+                                   [](const Range &a, uintptr_t v) { return a.b < v; });
+        if (it != yr.begin() && (it - 1)->e > x.b)
+            fail(SPMV_ERR_INVALID_ARG, "x of matrix %zu overlaps y of matrix %zu", x.i, (it - 1)->i);
     }
 }
 
@@ -509,9 +528,20 @@ extern "C" spmv_status spmv_batch_create(spmv_batch *out, const spmv_handle *hs,
     return st;
 }
 
-extern "C" spmv_status spmv_batch_run(spmv_batch b, void *stream) {
+extern "C" spmv_status spmv_batch_run(spmv_batch b, const double *alphas, const void *const *xs,
+                                      const double *betas, void *const *ys, void *stream) {
     return guard([&] {
         if (!b || !b->exec) fail(SPMV_ERR_INVALID_ARG, "NULL batch");
+        if (alphas || xs || betas || ys) {
+            std::vector<BatchDesc> keep = b->desc;
+            try {
+                set_io(b, xs, ys, alphas, betas);
+            } catch (...) {
+                b->desc = keep;
+                throw;
+            }
+            upload_desc(b, (hipStream_t)stream);
+        }
         SPMV_HIP(hipGraphLaunch(b->exec, (hipStream_t)stream));
     });
 }

@@ -147,7 +147,11 @@ def _dtype_code(dtype) -> int:
 
 
 def _buffer(a, want_dtype=None):
-    """(pointer, on_device, keepalive) for a torch tensor or NumPy array."""
+    """(pointer, on_device, keepalive) for a torch tensor or NumPy array.
+
+    A tensor must already have `want_dtype` (no silent reinterpretation); a host
+    array is converted to it, after a range check for integer targets.
+    """
     try:
         import torch
     except ImportError:  # pragma: no cover
@@ -155,18 +159,50 @@ def _buffer(a, want_dtype=None):
     if torch is not None and isinstance(a, torch.Tensor):
         if not a.is_contiguous():
             raise ValueError("tensor must be contiguous")
+        if want_dtype is not None and str(a.dtype) != "torch." + np.dtype(want_dtype).name:
+            raise ValueError(f"tensor dtype {a.dtype} where {np.dtype(want_dtype).name} is required")
         return ctypes.c_void_p(a.data_ptr() if a.numel() else 0), a.is_cuda, a
-    arr = np.ascontiguousarray(a, dtype=want_dtype) if want_dtype is not None else np.ascontiguousarray(a)
+    if want_dtype is not None:
+        src = np.asarray(a)
+        wd = np.dtype(want_dtype)
+        if wd.kind == "i" and src.size:
+            if src.dtype.kind not in "iu":
+                raise ValueError(f"integer indices required, got {src.dtype}")
+            info = np.iinfo(wd)
+            if src.min() < info.min or src.max() > info.max:
+                raise ValueError(f"index outside the {wd.name} range")
+        arr = np.ascontiguousarray(src, dtype=wd)
+    else:
+        arr = np.ascontiguousarray(a)
     return ctypes.c_void_p(arr.ctypes.data if arr.size else 0), False, arr
+
+
+def _check_vector(t, n, h, name):
+    """x / y of a run on handle h: a contiguous device tensor on h's device, of h's
+    value dtype, with at least n elements (checked before any call into the library)."""
+    want = "torch." + np.dtype(h.value_dtype).name
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if str(t.dtype) != want:
+        raise ValueError(f"{name} has dtype {t.dtype}, the matrix holds {want}")
+    if t.numel() < n:
+        raise ValueError(f"{name} has {t.numel()} elements, the matrix needs {n}")
+    dev = getattr(h, "device", None)
+    if dev is not None and t.device.index is not None and t.device.index != dev:
+        raise ValueError(f"{name} is on device {t.device.index}, the matrix on device {dev}")
+    return ctypes.c_void_p(t.data_ptr() if t.numel() else 0)
 
 
 class Handle:
     """Owns one spmv_handle; destroyed by spmv_destroy (or when collected)."""
 
-    def __init__(self, ptr, n_rows, n_cols, nnz, dtype_code):
+    def __init__(self, ptr, n_rows, n_cols, nnz, dtype_code, device=None):
         self.ptr = ptr
         self.n_rows, self.n_cols, self.nnz = n_rows, n_cols, nnz
         self.dtype_code = dtype_code
+        self.device = device  # the HIP device current at spmv_create
 
     @property
     def value_dtype(self):
@@ -188,11 +224,19 @@ def spmv_create(n_rows, n_cols, row, col, val, stream=None) -> Handle:
     pv, dv, kv = _buffer(val)
     if not (dr == dc == dv):
         raise ValueError("row, col and val must all be on the host or all on the device")
+    if not (len(kr.shape) == len(kc.shape) == len(kv.shape) == 1):
+        raise ValueError("row, col and val must be 1-D")
     nnz = int(kr.shape[0])
+    if int(kc.shape[0]) != nnz or int(kv.shape[0]) != nnz:
+        raise ValueError("row, col and val must have the same length")
+    import torch
+    device = torch.cuda.current_device() if torch.cuda.is_available() else None
+    if dr and device is not None and kr.device.index not in (None, device):
+        raise ValueError("device inputs must be on the current device")
     out = ctypes.c_void_p()
     _check(_lib.spmv_create(ctypes.byref(out), int(n_rows), int(n_cols), nnz, pr, pc, pv, dt,
                             int(dr), _stream_ptr(stream)), "spmv_create")
-    return Handle(out, int(n_rows), int(n_cols), nnz, dt)
+    return Handle(out, int(n_rows), int(n_cols), nnz, dt, device)
 
 
 def spmv_destroy(h: Handle):
@@ -214,8 +258,8 @@ def _device_buffer(a, name):
 
 def spmv_run(h: Handle, fmt: int, alpha, x, beta, y, stream=None):
     """y = alpha * A x + beta * y on the device (x, y: device tensors)."""
-    px = _device_buffer(x, "x")
-    py = _device_buffer(y, "y")
+    px = _check_vector(x, h.n_cols, h, "x")
+    py = _check_vector(y, h.n_rows, h, "y")
     _check(_lib.spmv_run(h.ptr, int(fmt), float(alpha), px, float(beta), py, _stream_ptr(stream)),
            "spmv_run")
 
@@ -251,8 +295,8 @@ def spmv_get_variant(h: Handle, fmt: int) -> int:
 def spmv_time(h: Handle, fmt: int, x, y, variant=-1, warmup=2, reps=10, flush=True,
               stream=None) -> np.ndarray:
     out = np.zeros(max(int(reps), 0), dtype=np.float32)
-    px = _device_buffer(x, "x")
-    py = _device_buffer(y, "y")
+    px = _check_vector(x, h.n_cols, h, "x")
+    py = _check_vector(y, h.n_rows, h, "y")
     _check(_lib.spmv_time(h.ptr, int(fmt), int(variant), px, py, int(warmup), int(reps),
                           int(bool(flush)), ctypes.c_void_p(out.ctypes.data if out.size else 0),
                           _stream_ptr(stream)), "spmv_time")
@@ -261,8 +305,8 @@ def spmv_time(h: Handle, fmt: int, x, y, variant=-1, warmup=2, reps=10, flush=Tr
 
 def spmv_tune(h: Handle, fmt: int, x, y, reps=10, flush=True, stream=None):
     """Time every variant of fmt, keep the fastest; returns (variant, median ms)."""
-    px = _device_buffer(x, "x")
-    py = _device_buffer(y, "y")
+    px = _check_vector(x, h.n_cols, h, "x")
+    py = _check_vector(y, h.n_rows, h, "y")
     bi, bm = _I32(), _F()
     _check(_lib.spmv_tune(h.ptr, int(fmt), px, py, int(reps), int(bool(flush)), ctypes.byref(bi),
                           ctypes.byref(bm), _stream_ptr(stream)), "spmv_tune")
@@ -366,7 +410,7 @@ class spmv_batch_config(ctypes.Structure):
 
 
 _sig("spmv_batch_create", _I32, ctypes.POINTER(_P), _P, _I32, _P, _P, _P, _P, ctypes.c_int, _P)
-_sig("spmv_batch_run", _I32, _P, _P)
+_sig("spmv_batch_run", _I32, _P, _P, _P, _P, _P, _P)
 _sig("spmv_batch_update", _I32, _P, _P, _P, _P, _P, _P)
 _sig("spmv_batch_get_config", _I32, _P, ctypes.POINTER(spmv_batch_config), _P)
 _sig("spmv_batch_set_config", _I32, _P, ctypes.POINTER(spmv_batch_config), _P)
@@ -385,37 +429,63 @@ class Batch:
             self.ptr = None
 
 
-def _ptr_array(items, name):
+def _ptr_array(items, name, handles=None, dim=None):
+    """Host array of device pointers; with handles, each tensor is checked against
+    its matrix (dtype, device, at least getattr(handle, dim) elements)."""
+    if handles is not None and len(items) != len(handles):
+        raise ValueError(f"{name} must have {len(handles)} entries")
     arr = (ctypes.c_void_p * len(items))()
     for i, t in enumerate(items):
-        arr[i] = _dev_ptr(t, f"{name}[{i}]").value
+        if handles is not None:
+            arr[i] = _check_vector(t, getattr(handles[i], dim), handles[i], f"{name}[{i}]").value
+        else:
+            arr[i] = _dev_ptr(t, f"{name}[{i}]").value
     return arr
 
 
 def spmv_batch_create(handles, xs, ys, alphas=None, betas=None, tune=True, stream=None) -> Batch:
     n = len(handles)
+    for name, arr in (("alphas", alphas), ("betas", betas)):
+        if arr is not None and len(arr) != n:
+            raise ValueError(f"{name} must have {n} entries")
     hs = (ctypes.c_void_p * n)(*[h.ptr.value if isinstance(h.ptr, ctypes.c_void_p) else h.ptr
                                  for h in handles])
     pa = (ctypes.c_double * n)(*alphas) if alphas is not None else None
     pb = (ctypes.c_double * n)(*betas) if betas is not None else None
     out = ctypes.c_void_p()
     _check(_lib.spmv_batch_create(ctypes.byref(out), ctypes.cast(hs, ctypes.c_void_p), n,
-                                  ctypes.cast(_ptr_array(xs, "xs"), ctypes.c_void_p),
-                                  ctypes.cast(_ptr_array(ys, "ys"), ctypes.c_void_p),
+                                  ctypes.cast(_ptr_array(xs, "xs", handles, "n_cols"), ctypes.c_void_p),
+                                  ctypes.cast(_ptr_array(ys, "ys", handles, "n_rows"), ctypes.c_void_p),
                                   ctypes.cast(pa, ctypes.c_void_p) if pa is not None else None,
                                   ctypes.cast(pb, ctypes.c_void_p) if pb is not None else None,
                                   int(bool(tune)), _stream_ptr(stream)), "spmv_batch_create")
     return Batch(out, handles, xs, ys)
 
 
-def spmv_batch_run(b: Batch, stream=None):
-    _check(_lib.spmv_batch_run(b.ptr, _stream_ptr(stream)), "spmv_batch_run")
+def spmv_batch_run(b: Batch, alphas=None, xs=None, betas=None, ys=None, stream=None):
+    """One graph launch of the batch; given alphas/xs/betas/ys replace the held ones."""
+    n = len(b.handles)
+    for name, arr in (("alphas", alphas), ("betas", betas)):
+        if arr is not None and len(arr) != n:
+            raise ValueError(f"{name} must have {n} entries")
+    pa = ctypes.cast((ctypes.c_double * n)(*alphas), ctypes.c_void_p) if alphas is not None else None
+    px = ctypes.cast(_ptr_array(xs, "xs", b.handles, "n_cols"), ctypes.c_void_p) if xs is not None else None
+    pb = ctypes.cast((ctypes.c_double * n)(*betas), ctypes.c_void_p) if betas is not None else None
+    py = ctypes.cast(_ptr_array(ys, "ys", b.handles, "n_rows"), ctypes.c_void_p) if ys is not None else None
+    _check(_lib.spmv_batch_run(b.ptr, pa, px, pb, py, _stream_ptr(stream)), "spmv_batch_run")
+    if xs is not None:
+        b.xs = list(xs)
+    if ys is not None:
+        b.ys = list(ys)
 
 
 def spmv_batch_update(b: Batch, xs=None, ys=None, alphas=None, betas=None, stream=None):
     n = len(b.handles)
-    px = ctypes.cast(_ptr_array(xs, "xs"), ctypes.c_void_p) if xs is not None else None
-    py = ctypes.cast(_ptr_array(ys, "ys"), ctypes.c_void_p) if ys is not None else None
+    for name, arr in (("alphas", alphas), ("betas", betas)):
+        if arr is not None and len(arr) != n:
+            raise ValueError(f"{name} must have {n} entries")
+    px = ctypes.cast(_ptr_array(xs, "xs", b.handles, "n_cols"), ctypes.c_void_p) if xs is not None else None
+    py = ctypes.cast(_ptr_array(ys, "ys", b.handles, "n_rows"), ctypes.c_void_p) if ys is not None else None
     pa = ctypes.cast((ctypes.c_double * n)(*alphas), ctypes.c_void_p) if alphas is not None else None
     pb = ctypes.cast((ctypes.c_double * n)(*betas), ctypes.c_void_p) if betas is not None else None
     _check(_lib.spmv_batch_update(b.ptr, px, py, pa, pb, _stream_ptr(stream)), "spmv_batch_update")

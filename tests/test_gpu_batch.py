@@ -101,12 +101,17 @@ def test_graph_replays_with_new_vectors_and_eager_work_between(tiling):
     b = S.spmv_batch_create(hs, xs, ys, alphas, zero_b, tune=False)
     if tiling == 2:
         S.spmv_batch_set_config(b, tiling=2, unroll=2, blocks_per_cu=2)
-    for rep in range(3):
+    for rep in range(4):
         new_x = [torch.from_numpy(synth.uniform_vector(m.n_cols, dtype, [m.seed, 100 + rep])).cuda()
                  for m in ms]
-        S.spmv_batch_update(b, xs=new_x)
-        junk = torch.randn(1 << 20, device="cuda")
-        S.spmv_batch_run(b)
+        if rep % 2 == 0:
+            S.spmv_batch_update(b, xs=new_x)
+            junk = torch.randn(1 << 20, device="cuda")
+            S.spmv_batch_run(b)
+        else:  # new vectors and scales passed to the run itself
+            alphas = [round(a * 0.5 - 0.25, 2) for a in alphas]
+            junk = torch.randn(1 << 20, device="cuda")
+            S.spmv_batch_run(b, alphas=alphas, xs=new_x, betas=zero_b)
         junk.mul_(2).sum().item()  # eager work and a sync between replays
         torch.cuda.synchronize()
         for i, m in enumerate(ms):
@@ -128,6 +133,22 @@ def test_batch_argument_errors():
         S.spmv_batch_set_config(b, tiling=0, unroll=4)
     assert e.value.status == "INVALID_ARG"
     S.spmv_batch_run(b)  # still valid with the old pointers
+    torch.cuda.synchronize()
+    # one launch computes every product: a y may not overlap another matrix's x or y
+    pool = torch.zeros(ms[0].n_rows + ms[1].n_rows + 8, dtype=torch.float32, device="cuda")
+    y_shared0 = pool[:ms[0].n_rows]
+    y_shared1 = pool[ms[0].n_rows - 4:ms[0].n_rows - 4 + ms[1].n_rows]
+    with pytest.raises(S.SpmvError) as e:
+        S.spmv_batch_run(b, ys=[y_shared0, y_shared1, ys[2]])
+    assert e.value.status == "INVALID_ARG"
+    xy = torch.zeros(max(ms[0].n_rows, ms[1].n_cols), dtype=torch.float32, device="cuda")
+    with pytest.raises(S.SpmvError) as e:  # x of matrix 1 is y of matrix 0
+        S.spmv_batch_update(b, xs=[xs[0], xy[:ms[1].n_cols], xs[2]], ys=[xy[:ms[0].n_rows], ys[1], ys[2]])
+    assert e.value.status == "INVALID_ARG"
+    # shared x vectors are fine (they are only read)
+    if ms[0].n_cols == ms[1].n_cols:
+        S.spmv_batch_update(b, xs=[xs[0], xs[0], xs[2]])
+    S.spmv_batch_run(b)
     torch.cuda.synchronize()
     h64 = S.spmv_create(4, 4, np.arange(4), np.arange(4), np.ones(4))
     with pytest.raises(S.SpmvError) as e:

@@ -299,9 +299,17 @@ def test_paper_printed_features_agree_with_definitions():
 
 
 def test_transform_features():
-    f = np.arange(12, dtype=np.float64)
+    # The selector input takes log2(1 + v) of the count and length features, the
+    # 1-based feature columns 1-7 (n, nnz, mean, var, std, median, mode), 9 (max)
+    # and 10 (bandwidth); columns 8 (ELL ratio), 11 (fill) and 12 (HYB tail
+    # fraction) are ratios and stay raw. The list is written out here, not read
+    # from the oracle.
+    log_cols_1based = [1, 2, 3, 4, 5, 6, 7, 9, 10]
+    f = np.array([7.0, 31.0, 3.0, 15.0, 0.5, 1.0, 63.0, 0.25, 255.0, 1023.0, 0.125, 0.75])
     t = F.transform_features(f)
     for i in range(12):
-        want = math.log2(1 + i) if i in F.LOG_FEATURES else i
-        assert t[i] == pytest.approx(want, rel=1e-15)
-    assert t[3] == 2.0 and t[7] == 7.0
+        want = math.log2(1 + f[i]) if (i + 1) in log_cols_1based else f[i]
+        assert t[i] == pytest.approx(want, rel=1e-15), i + 1
+    assert t.tolist() == [3.0, 5.0, 2.0, 4.0, math.log2(1.5), 1.0, 6.0, 0.25, 8.0, 10.0, 0.125, 0.75]
+    # batched rows are transformed column by column in the same way
+    assert np.array_equal(F.transform_features(np.stack([f, f]))[1], t)

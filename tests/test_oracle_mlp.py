@@ -97,6 +97,41 @@ def test_adam_first_step_closed_form():
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
 
 
+def test_adam_two_steps_by_hand():
+    # Kingma and Ba, Algorithm 1, worked by hand for one parameter with theta_0 = 0,
+    # gradients g_1 = 1 and g_2 = -2, alpha = 1e-3, beta1 = 0.9, beta2 = 0.999, eps = 1e-8:
+    #   m_1 = 0.1, v_1 = 0.001, both bias-corrected to 1, theta_1 = -1e-3 / (1 + 1e-8);
+    #   m_2 = 0.09 - 0.2 = -0.11, v_2 = 0.000999 + 0.004 = 0.004999,
+    #   m_hat = -0.11 / 0.19, v_hat = 0.004999 / 0.001999 (1 - 0.9^2, 1 - 0.999^2),
+    #   theta_2 = theta_1 - 1e-3 * m_hat / (sqrt(v_hat) + 1e-8), evaluated to 50 digits.
+    th, m, v = M.adam_step(np.zeros(1), np.array([1.0]), np.zeros(1), np.zeros(1), 1)
+    assert th[0] == pytest.approx(-0.00099999999000000009999999900000001, rel=1e-15)
+    th, m, v = M.adam_step(th, np.array([-2.0]), m, v, 2)
+    assert m[0] == pytest.approx(-0.11, rel=1e-15)
+    assert v[0] == pytest.approx(0.004999, rel=1e-15)
+    assert th[0] == pytest.approx(-0.00063389646527924911794492851072851, rel=1e-14)
+
+
+def test_adam_constant_gradient_through_train(monkeypatch):
+    # With a constant gradient g the bias-corrected moments are g and g^2 at every
+    # step t, so each update is exactly -lr * g / (|g| + eps) and after t steps
+    # theta_t = theta_0 - t * lr * g / (|g| + eps). Checked through train(), so a
+    # step counter that does not advance, or a correction stuck at t = 1, fails.
+    rng = np.random.default_rng(12)
+    g = rng.standard_normal(M.N_PARAMS) * 10.0 ** rng.integers(-3, 3, M.N_PARAMS)
+    monkeypatch.setattr(M, "loss_and_grad", lambda theta, Z, y, l2: (0.0, g.copy()))
+    theta0 = synth.glorot_params(13).astype(np.float64)
+    N = 10
+    Fr = np.abs(rng.standard_normal((N, 12))) + 1.0
+    perms = synth.epoch_permutations(13, N, 1)
+    for t in range(1, 6):
+        theta, _, _, losses = M.train(theta0, Fr, np.zeros(N, np.int64), perms, batch=2,
+                                      lr=1e-3, steps=t)
+        assert len(losses) == t
+        want = theta0 - t * 1e-3 * g / (np.abs(g) + 1e-8)
+        assert np.allclose(theta, want, rtol=0, atol=1e-14), t
+
+
 def test_standardisation():
     rng = np.random.default_rng(9)
     Fr = np.abs(rng.standard_normal((40, 12))) * 100
