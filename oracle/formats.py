@@ -150,6 +150,222 @@ def to_hyb(canon, k_override: int = -1) -> dict:
     }
 
 
+# ---- SELL-C-sigma (sliced ELL) ------------------------------------------------
+#
+# The paper's SELL paragraph (Background, popular SpMV formats): rows are cut
+# into slices of a constant number of rows, each slice is an ELL block as wide
+# as its longest row, and a slice index array points at each slice's start.
+# Readings where the paper leaves the layout open (listed in the design notes):
+#   * slice height C = 64 rows (one wavefront);
+#   * a slice's width is its longest row rounded up to a whole number of groups
+#     of G = 4 slots, and slot k of the row at position l of slice s sits at
+#     slice_ptr[s] + (k // G) * C * G + l * G + k % G (each row's slots come in
+#     runs of four, the runs of the slice's rows one after another);
+#   * sigma: rows may be reordered inside windows of sigma consecutive rows by
+#     descending length (stable), as in SELL-C-sigma (Kreutzer et al., SIAM J.
+#     Sci. Comput. 2014); sigma = 1 keeps the natural order, which is the
+#     paper's SELL. perm[p] is the row stored at position p;
+#   * padding slots hold column -1 and value +0.0, also the positions past the
+#     last row in the last slice; the slice pointers count slots (int64);
+#   * refused (NOT_APPLICABLE) when the slots exceed 8 * nnz, as for ELL, unless
+#     the layout is small (at most SMALL_LAYOUT_SLOTS slots);
+#   * the default sigma is the one of {1, 16384} whose layout stores fewer bytes
+#     (slots * (4 + v), plus 4 bytes per row for perm when sigma > 1), ties to 1.
+
+SELL_SLICE = 64
+SMALL_LAYOUT_SLOTS = 65536  # SELL slots / BELL values that are never refused
+SELL_GROUP = 4
+SELL_SIGMA_WIDE = 16384
+
+
+def sell_order(lengths, sigma: int) -> np.ndarray:
+    """perm[p] = row at position p: descending length inside each window of sigma rows (stable)."""
+    lengths = np.asarray(lengths, np.int64)
+    n = lengths.size
+    if sigma <= 1:
+        return np.arange(n, dtype=np.int32)
+    window = np.arange(n, dtype=np.int64) // sigma
+    # lexsort: last key primary -> window, then longer rows first, then row index
+    perm = np.lexsort((np.arange(n), -lengths, window))
+    return perm.astype(np.int32)
+
+
+def sell_slice_widths(lengths, perm, C=SELL_SLICE, G=SELL_GROUP) -> np.ndarray:
+    """Each slice's width: its longest row rounded up to a multiple of G."""
+    lengths = np.asarray(lengths, np.int64)
+    n = lengths.size
+    n_slices = -(-n // C)
+    w = np.zeros(n_slices, np.int64)
+    for s in range(n_slices):
+        rows = perm[s * C:(s + 1) * C]
+        m = int(lengths[rows].max()) if rows.size else 0
+        w[s] = -(-m // G) * G
+    return w
+
+
+def sell_sigma_rule(lengths, value_bytes: int) -> int:
+    """Default sigma: the candidate (1 or SELL_SIGMA_WIDE) whose layout stores fewer bytes."""
+    lengths = np.asarray(lengths, np.int64)
+    best, best_bytes = 1, None
+    for sigma in (1, SELL_SIGMA_WIDE):
+        w = sell_slice_widths(lengths, sell_order(lengths, sigma))
+        b = int(w.sum()) * SELL_SLICE * (4 + value_bytes) + (4 * lengths.size if sigma > 1 else 0)
+        if best_bytes is None or b < best_bytes:
+            best, best_bytes = sigma, b
+    return best
+
+
+def to_sell(canon, sigma: int = -1, C: int = SELL_SLICE, G: int = SELL_GROUP) -> dict:
+    """SELL-C-sigma layout of the canonical matrix (see the block comment above)."""
+    n = canon["n_rows"]
+    nnz = canon["col"].size
+    rp = np.asarray(canon["row_ptr"], np.int64)
+    lengths = row_lengths(rp)
+    vb = np.asarray(canon["val"]).dtype.itemsize
+    if sigma < 0:
+        sigma = sell_sigma_rule(lengths, vb) if n else 1
+    perm = sell_order(lengths, sigma)
+    widths = sell_slice_widths(lengths, perm, C, G)
+    slice_ptr = np.zeros(widths.size + 1, np.int64)
+    np.cumsum(widths * C, out=slice_ptr[1:])
+    slots = int(slice_ptr[-1])
+    if nnz > 0 and slots > max(ELL_FILL_CAP * nnz, SMALL_LAYOUT_SLOTS):
+        raise OracleError(NOT_APPLICABLE, f"SELL would hold {slots} slots for {nnz} entries")
+    col = np.full(slots, -1, np.int32)
+    val = np.zeros(slots, dtype=np.asarray(canon["val"]).dtype)
+    for p in range(n):
+        r = int(perm[p])
+        s, l = divmod(p, C)
+        k = np.arange(lengths[r], dtype=np.int64)
+        slot = slice_ptr[s] + (k // G) * C * G + l * G + k % G
+        col[slot] = canon["col"][rp[r]:rp[r + 1]]
+        val[slot] = canon["val"][rp[r]:rp[r + 1]]
+    return {"C": C, "G": G, "sigma": int(sigma), "n_slices": int(widths.size),
+            "slice_ptr": slice_ptr, "perm": perm, "col": col, "val": val}
+
+
+# ---- BELL (blocked ELL) ---------------------------------------------------------
+#
+# The paper's BELL paragraph: the ELL format over dense blocks, a data matrix of
+# blocks and a column index matrix of block indices, default block 2 x 2.
+# Readings (listed in the design notes):
+#   * square b x b blocks, b in {2, 4, 8}; block row i holds rows [b i, b i + b),
+#     block column j columns [b j, b j + b); a block is stored when it holds at
+#     least one entry; absent entries inside a stored block are +0.0 (so a
+#     non-finite x value meeting such a zero gives NaN, as in any blocked format);
+#   * block rows are ELL rows: width K_b = most stored blocks in one block row,
+#     the blocks of a block row in increasing block column, pitch = block rows
+#     rounded up to 64; slot (i, k) sits at k * pitch + i: bcol holds the block
+#     column (-1 for padding), bval holds the block's b * b values at
+#     (k * pitch + i) * b * b, row-major inside the block (zeros for padding);
+#   * refused (NOT_APPLICABLE) when the stored values (pitch * K_b * b^2) exceed
+#     8 * nnz, unless they are at most SMALL_LAYOUT_SLOTS;
+#   * the default b is the one of 2, 4, 8 within the cap whose layout stores the
+#     fewest bytes (pitch * K_b * (4 + b^2 v)), ties to the smaller block (2 when
+#     none is within the cap).
+
+BELL_SIZES = (2, 4, 8)
+
+
+def bell_block_counts(canon, b: int) -> np.ndarray:
+    """Stored blocks per block row for b x b blocks."""
+    n = canon["n_rows"]
+    nbr = -(-n // b)
+    r = np.asarray(canon["row"], np.int64) // b
+    c = np.asarray(canon["col"], np.int64) // b
+    keys = np.unique(r * (int(canon["n_cols"]) // b + 1) + c) if r.size else np.zeros(0, np.int64)
+    br = keys // (int(canon["n_cols"]) // b + 1)
+    return np.bincount(br, minlength=nbr).astype(np.int64) if nbr else np.zeros(0, np.int64)
+
+
+def bell_size_rule(canon, value_bytes: int) -> int:
+    """Default block edge: of the sizes within the fill cap, the one storing the fewest
+    bytes, ties to the smaller; 2 (the paper's default) when none is within the cap."""
+    nnz = canon["col"].size
+    best, best_bytes = BELL_SIZES[0], None
+    for b in BELL_SIZES:
+        cnt = bell_block_counts(canon, b)
+        K = int(cnt.max()) if cnt.size and nnz else 0
+        pitch = ell_pitch(cnt.size)
+        if nnz > 0 and pitch * K * b * b > max(ELL_FILL_CAP * nnz, SMALL_LAYOUT_SLOTS):
+            continue
+        by = pitch * K * (4 + b * b * value_bytes)
+        if best_bytes is None or by < best_bytes:
+            best, best_bytes = b, by
+    return best
+
+
+def to_bell(canon, b: int = -1) -> dict:
+    """BELL layout with b x b blocks (see the block comment above)."""
+    n, n_cols = canon["n_rows"], canon["n_cols"]
+    nnz = canon["col"].size
+    vdt = np.asarray(canon["val"]).dtype
+    if b < 0:
+        b = bell_size_rule(canon, vdt.itemsize)
+    if b not in BELL_SIZES:
+        raise OracleError(INVALID_ARG, f"block size {b}")
+    cnt = bell_block_counts(canon, b)
+    nbr = cnt.size
+    K = int(cnt.max()) if nbr and nnz else 0
+    pitch = ell_pitch(nbr)
+    if nnz > 0 and pitch * K * b * b > max(ELL_FILL_CAP * nnz, SMALL_LAYOUT_SLOTS):
+        raise OracleError(NOT_APPLICABLE, f"BELL would hold {pitch * K * b * b} values for {nnz} entries")
+    bcol = np.full(K * pitch, -1, np.int32)
+    bval = np.zeros(K * pitch * b * b, dtype=vdt)
+    # blocks of each block row in increasing block column: slot k = rank of the block
+    slot_of = {}
+    next_k = np.zeros(nbr, np.int64)
+    rows = np.asarray(canon["row"], np.int64)
+    cols = np.asarray(canon["col"], np.int64)
+    blocks = sorted(set(zip((rows // b).tolist(), (cols // b).tolist())))
+    for br, bc in blocks:
+        k = int(next_k[br])
+        next_k[br] += 1
+        slot_of[(br, bc)] = k
+        bcol[k * pitch + br] = bc
+    for e in range(nnz):
+        r, c = int(rows[e]), int(cols[e])
+        k = slot_of[(r // b, c // b)]
+        bval[(k * pitch + r // b) * b * b + (r % b) * b + (c % b)] = canon["val"][e]
+    return {"b": b, "K": K, "pitch": pitch, "n_block_rows": nbr, "bcol": bcol, "bval": bval}
+
+
+def sell_to_coo(sell: dict, n_rows: int):
+    """Stored (row, col, val) of a SELL layout, in (row, col) order."""
+    C, G = sell["C"], sell["G"]
+    rows, cols, vals = [], [], []
+    for s in range(sell["n_slices"]):
+        s0, s1 = int(sell["slice_ptr"][s]), int(sell["slice_ptr"][s + 1])
+        width = (s1 - s0) // C
+        for l in range(C):
+            p = s * C + l
+            if p >= n_rows:
+                continue
+            for k in range(width):
+                slot = s0 + (k // G) * C * G + l * G + k % G
+                if sell["col"][slot] >= 0:
+                    rows.append(int(sell["perm"][p]))
+                    cols.append(int(sell["col"][slot]))
+                    vals.append(sell["val"][slot])
+    order = np.lexsort((np.array(cols, np.int64), np.array(rows, np.int64))) if rows else []
+    return (np.array(rows, np.int32)[order], np.array(cols, np.int32)[order],
+            np.array(vals, dtype=np.asarray(sell["val"]).dtype)[order])
+
+
+def bell_to_dense(bell: dict, n_rows: int, n_cols: int) -> np.ndarray:
+    """Dense matrix a BELL layout stores (stored zeros and absent entries alike 0)."""
+    b, K, pitch = bell["b"], bell["K"], bell["pitch"]
+    d = np.zeros((bell["n_block_rows"] * b, (n_cols // b + 1) * b))
+    for k in range(K):
+        for i in range(bell["n_block_rows"]):
+            bc = int(bell["bcol"][k * pitch + i])
+            if bc < 0:
+                continue
+            blk = bell["bval"][(k * pitch + i) * b * b:(k * pitch + i + 1) * b * b].reshape(b, b)
+            d[i * b:(i + 1) * b, bc * b:(bc + 1) * b] = blk
+    return d[:n_rows, :n_cols]
+
+
 # ---- inverse maps, used by round-trip pins ---------------------------------
 
 def csr_to_coo_rows(row_ptr) -> np.ndarray:
