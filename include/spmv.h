@@ -49,9 +49,13 @@ typedef enum spmv_format {
     SPMV_FMT_CSR = 0, /* row_ptr[n_rows+1], col[nnz], val[nnz], rows in order    */
     SPMV_FMT_COO = 1, /* row[nnz], col[nnz], val[nnz], sorted by (row, col)       */
     SPMV_FMT_ELL = 2, /* col/val [K][pitch], column-major, pitch = roundup(n,64)  */
-    SPMV_FMT_HYB = 3  /* ELL part of width K_h + COO tail of the other entries    */
+    SPMV_FMT_HYB = 3, /* ELL part of width K_h + COO tail of the other entries    */
+    SPMV_FMT_SELL = 4,/* sliced ELL: slices of 64 rows, each as wide as its longest
+                         row (rounded up to 4 slots), slot pointers per slice, rows
+                         optionally reordered by length inside windows (sigma)    */
+    SPMV_FMT_BELL = 5 /* blocked ELL: ELL over dense b x b blocks, b = 2, 4 or 8  */
 } spmv_format;
-#define SPMV_NUM_FORMATS 4
+#define SPMV_NUM_FORMATS 6
 
 typedef enum spmv_dtype { SPMV_F32 = 0, SPMV_F64 = 1 } spmv_dtype;
 
@@ -82,6 +86,13 @@ typedef enum spmv_kernel {
                                    over a copy ordered by (panel, row, column), the
                                    first pass writing y, the others adding; only
                                    for matrices with more than one panel          */
+    SPMV_KERNEL_SELL = 9,       /* SELL: one wavefront per slice, lane l on the
+                                   slice's row l, four slots per 16-byte load;
+                                   ksplit > 1: the waves of a workgroup share one
+                                   slice, each taking every ksplit-th group       */
+    SPMV_KERNEL_BELL = 10,      /* BELL: `lanes` rows of a block per thread (b /
+                                   lanes threads per block row); a variant whose
+                                   `lanes` exceeds the layout's b does not apply */
     SPMV_KERNEL_CSR_STREAM = 8  /* CSR over row blocks of at most 256 rows and
                                    2048 entries: a workgroup streams its block's
                                    entries with 16-byte loads, keeps the products
@@ -129,6 +140,17 @@ typedef struct spmv_arrays {
     const void *ell_val;
     const int32_t *tail_row, *tail_col;
     const void *tail_val;
+    /* SELL: slot arrays in ell_col / ell_val; slice s holds slots
+     * [slice_ptr[s], slice_ptr[s+1]), slot k of the row at position l of the
+     * slice at slice_ptr[s] + (k / 4) * 256 + l * 4 + k % 4; perm[p] is the row
+     * at position p (NULL when sigma == 1: position p is row p).
+     * BELL: block columns in ell_col ([K][pitch], -1 = padding), block values
+     * in ell_val (block (i, k) at (k * pitch + i) * b * b, row-major), with
+     * K = most blocks in a block row, pitch = block rows rounded up to 64. */
+    int32_t sigma, n_slices, block;  /* SELL sigma and slices; BELL edge b       */
+    int64_t slots;                   /* SELL: slots; BELL: blocks (K * pitch)   */
+    const int64_t *slice_ptr;
+    const int32_t *perm;
 } spmv_arrays;
 
 /* ---- matrix lifetime ----------------------------------------------------- */
@@ -153,19 +175,32 @@ spmv_status spmv_create(spmv_handle *out, int32_t n_rows, int32_t n_cols, int64_
  * device. */
 void spmv_destroy(spmv_handle h);
 
-/* Build format `f` from the canonical CSR (paper, Background: ELL, and the
- * run-time mode's conversion step). CSR and COO exist after spmv_create and
- * return OK at once.
+/* Build format `f` from the canonical CSR (paper, Background: ELL, BELL and
+ * SELL, and the run-time mode's conversion step). CSR and COO exist after
+ * spmv_create and return OK at once. `param` is the format's layout parameter.
  *   ELL: width K = longest row, pitch = roundup(n_rows, 64), slot (i, k) at
  *        k * pitch + i, padding slots hold col -1 and val +0.0. Returns
  *        NOT_APPLICABLE (and builds nothing) when pitch * K > 8 * nnz.
  *   HYB: ELL part of width K_h plus the remaining entries as a COO tail in
- *        (row, col) order. hyb_k < 0 chooses K_h by the Bell-Garland rule:
+ *        (row, col) order. param < 0 chooses K_h by the Bell-Garland rule:
  *        the largest k such that at least T = min(n_rows, max(4096,
- *        ceil(n_rows/3))) rows hold k or more entries; hyb_k >= 0 forces it.
+ *        ceil(n_rows/3))) rows hold k or more entries; param >= 0 forces it.
+ *   SELL: param = sigma, the window inside which rows are reordered by
+ *        descending length (stable): 1 keeps the row order (the paper's SELL),
+ *        otherwise a positive multiple of 64; param < 0 takes whichever of 1
+ *        and 16384 stores fewer bytes (slots * (4 + value size), plus 4 bytes
+ *        per row for the order when sigma > 1; ties to 1). A slice's width is
+ *        its longest row rounded up to a multiple of 4; padding col -1, +0.0.
+ *   BELL: param = b in {2, 4, 8}; param < 0 takes, of the sizes within the
+ *        cap, the one storing the fewest bytes (pitch * K * (4 + b*b*value
+ *        size)), ties to the smaller, 2 if none. Absent entries of a stored
+ *        block are +0.0, so a non-finite x value meeting one gives NaN.
+ *   SELL and BELL return NOT_APPLICABLE when their slots (SELL) or stored
+ *        values (BELL) exceed both 8 * nnz and 65536.
  * A failed conversion leaves the handle's other formats intact.
- * Errors: INVALID_ARG, NOT_APPLICABLE, OOM, HIP. Synchronises `stream`. */
-spmv_status spmv_convert(spmv_handle h, spmv_format f, int32_t hyb_k, void *stream);
+ * Errors: INVALID_ARG (bad param), NOT_APPLICABLE, OOM, HIP. Synchronises
+ * `stream`. */
+spmv_status spmv_convert(spmv_handle h, spmv_format f, int32_t param, void *stream);
 
 /* y = alpha * A * x + beta * y with the handle's current variant for `f`
  * (paper, Background: SpMV processing on GPU). Asynchronous on `stream`.
@@ -237,9 +272,10 @@ spmv_status spmv_features(spmv_handle h, float *out12, void *stream);
  *          (requires spmv_selector_set_weights; else NO_MODEL).
  *   EXHAUSTIVE: convert every format, tune each, take the fastest median.
  *   RULE: fixed thresholds on the features.
- *   out: host pointer. out_scores: host float[4] or NULL: logits (MODEL),
- *   best median ms per format, +inf if not applicable (EXHAUSTIVE), or 0/1
- *   votes (RULE). The chosen format is converted before return.
+ *   out: host pointer. out_scores: host float[SPMV_NUM_FORMATS] or NULL:
+ *   logits (MODEL; -inf for a format the installed network has no class
+ *   for), best median ms per format, +inf if not applicable (EXHAUSTIVE), or
+ *   0/1 votes (RULE). The chosen format is converted before return.
  * Errors: INVALID_ARG, NO_MODEL, OOM, HIP. Synchronises `stream`. */
 spmv_status spmv_select_format(spmv_handle h, spmv_select_mode m, spmv_format *out,
                                float *out_scores, void *stream);
@@ -318,14 +354,17 @@ void spmv_batch_destroy(spmv_batch b);
  * parameters -- a classifier over the sparsity features; Setup, learning
  * algorithms: MLP with ReLU, Adam, learning rate 0.001, 200 epochs) -----------
  *
- * Network 12-64-64-4 with ReLU; classes are spmv_format values. A model is
- * 5276 floats: W1[64][12] b1[64] W2[64][64] b2[64] W3[4][64] b3[4] (5252
- * parameters, each W row-major [out][in]) then the input standardisation
+ * Network 12-64-64-C with ReLU, C = 4 classes (CSR, COO, ELL, HYB) or C = 6
+ * (also SELL, BELL); classes are spmv_format values. A model is W1[64][12]
+ * b1[64] W2[64][64] b2[64] W3[C][64] b3[C] (each W row-major [out][in]; 5252
+ * parameters for C = 4, 5382 for C = 6) then the input standardisation
  * mean[12], std[12]. Inputs are the 12 features of spmv_features with
  * log2(1 + v) applied to features 0-6, 8 and 9, then (v - mean) / std. */
 
-#define SPMV_SELECTOR_PARAMS 5252
+#define SPMV_SELECTOR_PARAMS 5252  /* C = 4 */
 #define SPMV_SELECTOR_MODEL 5276
+#define SPMV_SELECTOR_PARAMS6 5382 /* C = 6 */
+#define SPMV_SELECTOR_MODEL6 5406
 
 typedef struct spmv_train_opts {
     int32_t epochs;    /* passes over the data (200)                              */
@@ -334,46 +373,55 @@ typedef struct spmv_train_opts {
     float lr;          /* Adam step size (1e-3)                                   */
     float l2;          /* L2 weight alpha; the loss adds alpha/(2B)*|W|^2 (1e-4)   */
     float beta1, beta2, eps; /* Adam (0.9, 0.999, 1e-8)                           */
+    int32_t classes;   /* 4 or 6 (0 means 4)                                      */
 } spmv_train_opts;
 
 /* Train the selector on the device: mean softmax cross-entropy + L2, minibatch
  * Adam (Kingma and Ba, Algorithm 1) in the sample order perms gives for each
  * epoch; the standardisation statistics are the training set's mean and
  * population std (floored at 1e-6). One workgroup runs every step in one
- * launch (deterministic).
- *   feats: device float[n][12] raw features; labels: device int32[n] in 0..3;
- *   init_params: device float[5252]; perms: device int32[epochs][n], each row a
- *   permutation of 0..n-1; out_model: device float[5276];
- *   out_losses: device float[number of steps] or NULL (loss of each step).
- * Errors: INVALID_ARG, OOM, HIP. Synchronises `stream`. */
+ * launch (deterministic). The initial weights and the epoch orders are inputs
+ * (the caller draws them; the library draws no random numbers).
+ *   feats: device float[n][12] raw features; labels: device int32[n] in
+ *   0..C-1; init_params: device float[params of C]; perms: device
+ *   int32[epochs][n], each row a permutation of 0..n-1; out_model: device
+ *   float[model of C]; out_losses: device float[number of steps] or NULL.
+ * Errors: INVALID_ARG (also a label or order entry out of range), OOM, HIP.
+ * Synchronises `stream`. */
 spmv_status spmv_selector_train(const float *feats, const int32_t *labels, int32_t n,
                                 const float *init_params, const int32_t *perms,
                                 const spmv_train_opts *opts, float *out_model, float *out_losses,
                                 void *stream);
 
 /* Loss and gradient of one minibatch (the quantities a training step uses):
- *   params: device float[5252]; z: device float[b][12] already standardised;
- *   labels: device int32[b]; loss: device float[1]; grad: device float[5252].
+ *   params: device float[params of C]; classes: C (4 or 6); z: device
+ *   float[b][12] already standardised; labels: device int32[b]; loss: device
+ *   float[1]; grad: device float[params of C].
  * Asynchronous on `stream`. Errors: INVALID_ARG, HIP. */
-spmv_status spmv_selector_loss_grad(const float *params, const float *z, const int32_t *labels,
-                                    int32_t b, float l2, float *loss, float *grad, void *stream);
+spmv_status spmv_selector_loss_grad(const float *params, int32_t classes, const float *z,
+                                    const int32_t *labels, int32_t b, float l2, float *loss,
+                                    float *grad, void *stream);
 
 /* Logits and chosen class for n feature vectors.
- *   model: device float[5276], or NULL for the weights set on this device;
- *   feats: device float[n][12] raw features; applicable: device uint8[n][4]
- *   (nonzero = format allowed) or NULL for all; logits: device float[n][4] or
- *   NULL; cls: device int32[n] or NULL (arg-max over allowed classes, ties to
- *   the lowest). Asynchronous. Errors: INVALID_ARG, NO_MODEL, HIP. */
-spmv_status spmv_selector_predict(const float *model, const float *feats, int32_t n,
-                                  const uint8_t *applicable, float *logits, int32_t *cls,
-                                  void *stream);
+ *   model: device float[model of C] with classes = C, or NULL for the network
+ *   installed on this device (classes 0 or its C); feats: device float[n][12]
+ *   raw features; applicable: device uint8[n][C] (nonzero = format allowed) or
+ *   NULL for all; logits: device float[n][C] or NULL; cls: device int32[n] or
+ *   NULL (arg-max over allowed classes, ties to the lowest). Asynchronous.
+ * Errors: INVALID_ARG, NO_MODEL, HIP. */
+spmv_status spmv_selector_predict(const float *model, int32_t classes, const float *feats,
+                                  int32_t n, const uint8_t *applicable, float *logits,
+                                  int32_t *cls, void *stream);
 
-/* Install / read the weights MODEL selection uses on the current device.
- *   params: host float[5276]; n must be 5276. set_weights(NULL, 0) forgets the
- *   model (MODEL selection then returns NO_MODEL).
+/* Install / read the network MODEL selection uses on the current device.
+ *   params: host float[n], n = 5276 (C = 4) or 5406 (C = 6);
+ *   set_weights(NULL, 0) forgets it (MODEL selection then returns NO_MODEL).
+ *   get_weights wants n equal to the installed model's size.
  * Errors: INVALID_ARG, NO_MODEL (get before set), HIP. Synchronous. */
 spmv_status spmv_selector_set_weights(const float *params, int64_t n);
 spmv_status spmv_selector_get_weights(float *params, int64_t n);
+/* Classes of the network installed on the current device (0: none). */
+int32_t spmv_selector_classes(void);
 
 /* ---- diagnostics ------------------------------------------------------------ */
 

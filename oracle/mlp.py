@@ -6,7 +6,8 @@ The paper selects the sparse format with a classifier over sparsity features
 (Method: predicting optimal configuration parameters, multi-class
 classification) and reports an MLP trained with ReLU, Adam and learning rate
 0.001 for 200 epochs, other settings left at scikit-learn defaults (Learning
-Algorithms section and its model table). Here the network is 12-64-64-4:
+Algorithms section and its model table). Here the network is 12-64-64-C, C = 4 classes (CSR, COO,
+ELL, HYB) or 6 (also SELL, BELL):
 
   h1 = ReLU(W1 z + b1), h2 = ReLU(W2 h1 + b2), logits = W3 h2 + b3,
 
@@ -26,19 +27,32 @@ from .formats import transform_features
 LAYERS = (12, 64, 64, 4)
 N_PARAMS = 5252
 STD_FLOOR = 1e-6
+HIDDEN_PARAMS = 12 * 64 + 64 + 64 * 64 + 64  # every parameter before W3
+
+
+def classes_of(params) -> int:
+    """Output classes of a flat parameter vector: 4 (CSR, COO, ELL, HYB) or 6 (also SELL, BELL)."""
+    rest = np.asarray(params).size - HIDDEN_PARAMS
+    assert rest > 0 and rest % 65 == 0, "not a 12-64-64-C parameter vector"
+    return rest // 65
+
+
+def n_params(classes: int) -> int:
+    return HIDDEN_PARAMS + 65 * classes
 
 
 def unpack(params):
     p = np.asarray(params, dtype=np.float64)
+    layers = LAYERS[:-1] + (classes_of(p),)
     out = []
     off = 0
-    for fi, fo in zip(LAYERS[:-1], LAYERS[1:]):
+    for fi, fo in zip(layers[:-1], layers[1:]):
         W = p[off:off + fo * fi].reshape(fo, fi)
         off += fo * fi
         b = p[off:off + fo]
         off += fo
         out.append((W, b))
-    assert off == p.size == N_PARAMS
+    assert off == p.size
     return out
 
 

@@ -35,7 +35,7 @@ void fail(spmv_status s, const char *fmt, ...) {
     throw Error{s};
 }
 
-bool valid_format(spmv_format f) { return f >= SPMV_FMT_CSR && f <= SPMV_FMT_HYB; }
+bool valid_format(spmv_format f) { return f >= SPMV_FMT_CSR && f <= SPMV_FMT_BELL; }
 
 bool format_built(const spmv_matrix_s *h, spmv_format f) {
     switch (f) {
@@ -43,6 +43,8 @@ bool format_built(const spmv_matrix_s *h, spmv_format f) {
         case SPMV_FMT_COO: return true;
         case SPMV_FMT_ELL: return h->ell.built;
         case SPMV_FMT_HYB: return h->hyb.built;
+        case SPMV_FMT_SELL: return h->sell.built;
+        case SPMV_FMT_BELL: return h->bell.built;
     }
     return false;
 }
@@ -53,12 +55,18 @@ void check_runnable(const spmv_matrix_s *h, spmv_format f) {
     if (!format_built(h, f)) fail(SPMV_ERR_NOT_CONVERTED, "format %d not converted", (int)f);
 }
 
-void convert(spmv_matrix_s *h, spmv_format f, int32_t hyb_k, hipStream_t s) {
+void convert(spmv_matrix_s *h, spmv_format f, int32_t param, hipStream_t s) {
     switch (f) {
         case SPMV_FMT_CSR:
         case SPMV_FMT_COO: return;
         case SPMV_FMT_ELL: build_ell(h, s); return;
-        case SPMV_FMT_HYB: build_hyb(h, hyb_k, s); return;
+        case SPMV_FMT_HYB: build_hyb(h, param, s); return;
+        case SPMV_FMT_SELL: build_sell(h, param, s); return;
+        case SPMV_FMT_BELL:
+            build_bell(h, param, s);
+            // the variant must fit the new block size
+            if (!variant_applicable(h, f, h->variant[f])) h->variant[f] = default_variant(h, f);
+            return;
     }
 }
 
@@ -79,7 +87,7 @@ int env_int(const char *name, int dflt) {
 }
 
 // Timing-based choice: every applicable format converted, tuned and timed.
-spmv_format select_exhaustive(spmv_matrix_s *h, float scores[4], hipStream_t s) {
+spmv_format select_exhaustive(spmv_matrix_s *h, float scores[SPMV_NUM_FORMATS], hipStream_t s) {
     const size_t vs = dtype_size(h->dt);
     DevBuf x, y;
     x.alloc(std::max<int64_t>(h->n_cols, 1) * vs);
@@ -116,19 +124,20 @@ spmv_format select_exhaustive(spmv_matrix_s *h, float scores[4], hipStream_t s) 
 // HYB when a few rows are far longer than the rest and its COO tail stays
 // small, COO (the column-sorted block kernel) for large matrices with rows of
 // 16 or more entries, ELL when it pads little, CSR otherwise.
-spmv_format select_rule(const float f[12], float votes[4]) {
+spmv_format select_rule(const float f[12], float votes[SPMV_NUM_FORMATS]) {
     const double nnz = f[1], mean = f[2], ell_ratio = f[7], mx = f[8], tail = f[11];
     spmv_format r = SPMV_FMT_CSR;
     if (mean > 0 && mx > 32 * mean && tail < 0.3) r = SPMV_FMT_HYB;
     else if (mean >= 16 && nnz >= 4e6) r = SPMV_FMT_COO;
     else if (ell_ratio >= 0.9) r = SPMV_FMT_ELL;
-    for (int i = 0; i < 4; ++i) votes[i] = (i == (int)r) ? 1.f : 0.f;
+    for (int i = 0; i < SPMV_NUM_FORMATS; ++i) votes[i] = (i == (int)r) ? 1.f : 0.f;
     return r;
 }
 
 }  // namespace
 
 bool prepare_variant(spmv_matrix_s *h, spmv_format f, int32_t idx, hipStream_t s) {
+    if (!variant_applicable(h, f, idx)) return false;
     try {
         if (variant_needs_panel(f, idx) && !h->panel.built) build_panel(h, s);
         if (variant_needs_sorted(f, idx) && !h->sorted.built) build_sorted(h, s);
@@ -143,8 +152,38 @@ bool prepare_variant(spmv_matrix_s *h, spmv_format f, int32_t idx, hipStream_t s
     return true;
 }
 
-spmv_status select_model(spmv_matrix_s *h, const float feats[12], spmv_format *out, float scores[4],
+spmv_status model_logits(const float *feats, float scores[SPMV_NUM_FORMATS], int *classes,
                          hipStream_t s);  // mlp.hip
+
+// The network's choice: the highest logit over the formats it has classes for
+// (ties to the lowest), ELL left out when its padding cap refuses it; a choice
+// whose conversion is refused (SELL, BELL) gives way to the next highest.
+spmv_format select_model(spmv_matrix_s *h, const float feats[12], float scores[SPMV_NUM_FORMATS],
+                         hipStream_t s) {
+    int nc = 0;
+    const spmv_status st = model_logits(feats, scores, &nc, s);
+    if (st != SPMV_OK) throw Error{st};
+    bool allowed[SPMV_NUM_FORMATS];
+    for (int i = 0; i < SPMV_NUM_FORMATS; ++i) allowed[i] = i < nc;
+    const bool ell_ok = h->nnz == 0 ||
+                        (int64_t)((h->n_rows + 63) / 64 * 64) * h->stats.max_len <= 8 * h->nnz;
+    allowed[SPMV_FMT_ELL] = allowed[SPMV_FMT_ELL] && ell_ok;
+    for (;;) {
+        int best = SPMV_FMT_CSR;
+        for (int i = 0; i < SPMV_NUM_FORMATS; ++i)
+            if (allowed[i] && (!allowed[best] || scores[i] > scores[best])) best = i;
+        const spmv_format f = (spmv_format)best;
+        if (format_built(h, f)) return f;
+        try {
+            convert(h, f, -1, s);
+            return f;
+        } catch (const Error &e) {
+            if (e.status != SPMV_ERR_NOT_APPLICABLE) throw;
+            clear_error();
+            allowed[best] = false;  // CSR and COO always exist, so this ends
+        }
+    }
+}
 
 }  // namespace spmv
 
@@ -156,11 +195,11 @@ extern "C" void spmv_destroy(spmv_handle h) {
     delete h;
 }
 
-extern "C" spmv_status spmv_convert(spmv_handle h, spmv_format f, int32_t hyb_k, void *stream) {
+extern "C" spmv_status spmv_convert(spmv_handle h, spmv_format f, int32_t param, void *stream) {
     return guard([&] {
         if (!h) fail(SPMV_ERR_INVALID_ARG, "NULL handle");
         if (!valid_format(f)) fail(SPMV_ERR_INVALID_ARG, "bad format %d", (int)f);
-        convert(h, f, hyb_k, (hipStream_t)stream);
+        convert(h, f, param, (hipStream_t)stream);
         // a new HYB split drops the old tail's sorted copy: the current variant rebuilds it
         if (f == SPMV_FMT_HYB) (void)prepare_variant(h, f, h->variant[f], (hipStream_t)stream);
     });
@@ -219,6 +258,23 @@ extern "C" spmv_status spmv_get_arrays(spmv_handle h, spmv_format f, spmv_arrays
                 v->tail_col = h->hyb.tail_col.as<int32_t>();
                 v->tail_val = h->hyb.tail_val.p;
                 break;
+            case SPMV_FMT_SELL:
+                v->sigma = h->sell.sigma;
+                v->n_slices = h->sell.n_slices;
+                v->slots = h->sell.slots;
+                v->slice_ptr = h->sell.slice_ptr.as<int64_t>();
+                v->perm = h->sell.sigma > 1 ? h->sell.perm.as<int32_t>() : nullptr;
+                v->ell_col = h->sell.col.as<int32_t>();
+                v->ell_val = h->sell.val.p;
+                break;
+            case SPMV_FMT_BELL:
+                v->block = h->bell.b;
+                v->K = h->bell.K;
+                v->pitch = h->bell.pitch;
+                v->slots = (int64_t)h->bell.K * h->bell.pitch;
+                v->ell_col = h->bell.col.as<int32_t>();
+                v->ell_val = h->bell.val.p;
+                break;
         }
     });
 }
@@ -265,7 +321,7 @@ extern "C" spmv_status spmv_select_format(spmv_handle h, spmv_select_mode m, spm
     return guard([&] {
         if (!h || !out) fail(SPMV_ERR_INVALID_ARG, "NULL argument");
         hipStream_t s = (hipStream_t)stream;
-        float scores[4] = {0, 0, 0, 0};
+        float scores[SPMV_NUM_FORMATS] = {};
         spmv_format f = SPMV_FMT_CSR;
         if (m == SPMV_SELECT_EXHAUSTIVE) {
             f = select_exhaustive(h, scores, s);
@@ -278,8 +334,7 @@ extern "C" spmv_status spmv_select_format(spmv_handle h, spmv_select_mode m, spm
                     (int64_t)((h->n_rows + 63) / 64 * 64) * h->stats.max_len > 8 * h->nnz)
                     f = SPMV_FMT_CSR;
             } else {
-                spmv_status st = select_model(h, feats, &f, scores, s);
-                if (st != SPMV_OK) throw Error{st};
+                f = select_model(h, feats, scores, s);
             }
             if (!format_built(h, f)) convert(h, f, -1, s);
         } else {

@@ -163,6 +163,31 @@ struct SplitPart {
 };
 inline int32_t split_width(spmv_dtype dt) { return dt == SPMV_F64 ? (1 << 18) : (1 << 19); }
 
+// SELL-C-sigma: slices of kSellSlice rows; slice s holds slots [slice_ptr[s],
+// slice_ptr[s + 1]), its width (slots per row) a multiple of kSellGroup; slot k
+// of the row at position l sits at slice_ptr[s] + (k / 4) * 256 + l * 4 + k % 4.
+// perm[p] is the row at position p (only when sigma > 1).
+constexpr int kSellSlice = 64;
+constexpr int kSellGroup = 4;
+constexpr int32_t kSellSigmaWide = 16384;
+constexpr int64_t kSmallLayoutSlots = 65536;  // SELL / BELL layouts never refused
+
+struct SellPart {
+    bool built = false;
+    int32_t sigma = 1, n_slices = 0;
+    int64_t slots = 0;
+    std::vector<int64_t> host_ptr;  // slice pointers (host copy)
+    DevBuf slice_ptr, perm, col, val;
+};
+
+// BELL: b x b blocks, ELL over block rows: bcol[k * pitch + i] the block column
+// (-1 padding), bval[(k * pitch + i) * b * b + r * b + c].
+struct BellPart {
+    bool built = false;
+    int32_t b = 2, K = 0, pitch = 0, n_block_rows = 0;
+    DevBuf col, val;
+};
+
 // Row-length statistics kept from ingest (used by defaults and features).
 struct RowStats {
     int32_t max_len = 0;
@@ -200,8 +225,10 @@ struct spmv_matrix_s {
     spmv::SortedPart hyb_sorted;  // the HYB tail's, built on first use of a sorted-tail HYB variant
     spmv::SplitPart split;    // built on first use of a column-split COO variant
     spmv::CsrBlocks csr_blocks;  // built on first use of a CSR stream variant
+    spmv::SellPart sell;
+    spmv::BellPart bell;
     spmv::RowStats stats;
-    int32_t variant[SPMV_NUM_FORMATS] = {0, 0, 0, 0};
+    int32_t variant[SPMV_NUM_FORMATS] = {};
 };
 
 namespace spmv {
@@ -218,6 +245,8 @@ int32_t device_max_row_len(const int32_t *row_ptr, int32_t n_rows, hipStream_t s
 // convert.hip
 void build_ell(spmv_matrix_s *h, hipStream_t s);
 void build_hyb(spmv_matrix_s *h, int32_t hyb_k, hipStream_t s);
+void build_sell(spmv_matrix_s *h, int32_t sigma, hipStream_t s);  // sigma < 0: rule
+void build_bell(spmv_matrix_s *h, int32_t b, hipStream_t s);      // b < 0: rule
 int32_t hyb_rule_width(spmv_matrix_s *h, hipStream_t s);
 
 // panel.hip
@@ -260,6 +289,9 @@ void sorted_spmv(const spmv_matrix_s *h, int items, double alpha, const void *x,
 int32_t variant_count(spmv_format f, spmv_dtype dt);
 bool variant_describe(spmv_format f, spmv_dtype dt, int32_t idx, spmv_variant_info *out);
 int32_t default_variant(const spmv_matrix_s *h, spmv_format f);
+// False when variant idx cannot run on the layout f holds now (BELL: more rows
+// per thread than the block has).
+bool variant_applicable(const spmv_matrix_s *h, spmv_format f, int32_t idx);
 bool variant_needs_panel(spmv_format f, int32_t idx);
 bool variant_needs_sorted(spmv_format f, int32_t idx);
 bool variant_needs_hyb_sorted(spmv_format f, int32_t idx);
@@ -301,6 +333,6 @@ __device__ __forceinline__ T ld_stream(const T *p) {
     return __builtin_nontemporal_load(p);
 }
 
-inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+constexpr int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace spmv

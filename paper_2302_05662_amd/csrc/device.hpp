@@ -70,6 +70,36 @@ __device__ __forceinline__ Pack<double, N> ld_val(const double *p) {
     return r;
 }
 
+// N consecutive x values (a cached load, x is reused): vector loads of up to 16
+// bytes when p is aligned to them, element loads otherwise.
+template <class V, int N>
+__device__ __forceinline__ Pack<V, N> ld_xrun(const V *p) {
+    Pack<V, N> r;
+    constexpr int W = (N * (int)sizeof(V) >= 16) ? 16 / (int)sizeof(V) : N;  // values per load
+    if (((uintptr_t)p % (W * sizeof(V))) == 0) {
+#pragma unroll
+        for (int q = 0; q < N; q += W) {
+            if constexpr (W == 4) {
+                const f32x4 a = *(const f32x4 *)(p + q);
+                r.v[q] = a.x; r.v[q + 1] = a.y; r.v[q + 2] = a.z; r.v[q + 3] = a.w;
+            } else if constexpr (W == 2 && sizeof(V) == 8) {
+                const f64x2 a = *(const f64x2 *)(p + q);
+                r.v[q] = a.x; r.v[q + 1] = a.y;
+            } else if constexpr (W == 2) {
+                const f32x2 a = *(const f32x2 *)(p + q);
+                r.v[q] = a.x; r.v[q + 1] = a.y;
+            } else {
+#pragma unroll
+                for (int j = 0; j < W; ++j) r.v[q + j] = p[q + j];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j) r.v[j] = p[j];
+    }
+    return r;
+}
+
 // y_i = alpha * s + beta * y_i, with y not read when beta == 0.
 template <class V>
 __device__ __forceinline__ void store_y(V *y, int64_t i, double s, V alpha, V beta) {

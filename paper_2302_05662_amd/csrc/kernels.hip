@@ -560,6 +560,243 @@ __global__ __launch_bounds__(256) void coo_fixup(int64_t nnz, int64_t n_tiles,
     else store_y(y, r_last, s, alpha, beta);
 }
 
+// ---- SELL-C-sigma: one wavefront per slice of 64 rows --------------------------------
+//
+// Lane l owns the row at position l of its slice; each 16-byte load brings four
+// consecutive slots of that row (the slice stores its rows' slots in runs of
+// four), so a wavefront reads 1 KB contiguous per value array and group.
+// UNROLL groups are loaded before their gathers are issued; with PIPE the next
+// step's loads are in flight during the current gathers (buffers alternate by
+// unrolling, as in the pipelined ELL kernel). KS > 1: the KS waves of a
+// workgroup share one slice, wave w taking groups w, w + KS, ..., and their
+// partial sums meet in LDS in wave order (for slices too wide for one wave).
+
+template <class V, int UNROLL>
+struct SellStep {
+    Pack<int32_t, 4> c[UNROLL];
+    Pack<V, 4> v[UNROLL];
+};
+
+template <class V, int UNROLL>
+__device__ __forceinline__ void sell_load(SellStep<V, UNROLL> &st, const int32_t *__restrict__ col,
+                                          const V *__restrict__ val, int64_t base, int32_t g,
+                                          int32_t gstride, int32_t groups, int lane) {
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+        const int32_t gu = g + u * gstride;
+        const int64_t off = base + (int64_t)(gu < groups ? gu : 0) * (kSellSlice * kSellGroup) + lane * 4;
+        st.c[u] = ld_i32<4>(col + off);
+        st.v[u] = ld_val<4>(val + off);
+        if (gu >= groups)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) st.c[u].v[q] = -1;
+    }
+}
+
+template <class V, int UNROLL>
+__device__ __forceinline__ void sell_accumulate(const SellStep<V, UNROLL> &st,
+                                                const V *__restrict__ x, double &acc) {
+    V xv[UNROLL][4];
+    bool ok[UNROLL][4];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            ok[u][q] = st.c[u].v[q] >= 0;
+            xv[u][q] = x[ok[u][q] ? st.c[u].v[q] : 0];
+        }
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double prod = (double)st.v[u].v[q] * (double)xv[u][q];
+            acc += ok[u][q] ? prod : 0.0;
+        }
+}
+
+// Sum of the slots of one row of a slice, groups g0, g0 + gstride, ... < groups.
+template <class V, int UNROLL, bool PIPE>
+__device__ __forceinline__ double sell_row_sum(const int32_t *__restrict__ col,
+                                               const V *__restrict__ val, const V *__restrict__ x,
+                                               int64_t base, int32_t groups, int32_t g0,
+                                               int32_t gstride, int lane) {
+    double acc = 0.0;
+    const int32_t step = UNROLL * gstride;
+    if constexpr (!PIPE) {
+        for (int32_t g = g0; g < groups; g += step) {
+            SellStep<V, UNROLL> st;
+            sell_load<V, UNROLL>(st, col, val, base, g, gstride, groups, lane);
+            __builtin_amdgcn_sched_barrier(0);
+            sell_accumulate<V, UNROLL>(st, x, acc);
+        }
+    } else {
+        if (g0 >= groups) return 0.0;
+        SellStep<V, UNROLL> A, B;
+        sell_load<V, UNROLL>(A, col, val, base, g0, gstride, groups, lane);
+        int32_t g = g0;
+        for (;;) {
+            // gathers of A, then B's loads, then A's products
+            V xv[UNROLL][4];
+            bool ok[UNROLL][4];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    ok[u][q] = A.c[u].v[q] >= 0;
+                    xv[u][q] = x[ok[u][q] ? A.c[u].v[q] : 0];
+                }
+            __builtin_amdgcn_sched_barrier(0);
+            const bool more = g + step < groups;
+            sell_load<V, UNROLL>(B, col, val, base, more ? g + step : g0, gstride, groups, lane);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double prod = (double)A.v[u].v[q] * (double)xv[u][q];
+                    acc += ok[u][q] ? prod : 0.0;
+                }
+            if (!more) break;
+            g += step;
+            // same body with the buffers swapped
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    ok[u][q] = B.c[u].v[q] >= 0;
+                    xv[u][q] = x[ok[u][q] ? B.c[u].v[q] : 0];
+                }
+            __builtin_amdgcn_sched_barrier(0);
+            const bool more2 = g + step < groups;
+            sell_load<V, UNROLL>(A, col, val, base, more2 ? g + step : g0, gstride, groups, lane);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double prod = (double)B.v[u].v[q] * (double)xv[u][q];
+                    acc += ok[u][q] ? prod : 0.0;
+                }
+            if (!more2) break;
+            g += step;
+        }
+    }
+    return acc;
+}
+
+template <class V, int BLOCK, int UNROLL, bool PIPE, bool PERM>
+__global__ __launch_bounds__(BLOCK) void sell_kernel(int32_t n_rows, int32_t n_slices,
+                                                     const int64_t *__restrict__ slice_ptr,
+                                                     const int32_t *__restrict__ perm,
+                                                     const int32_t *__restrict__ col,
+                                                     const V *__restrict__ val,
+                                                     const V *__restrict__ x, V alpha, V beta,
+                                                     V *__restrict__ y) {
+    constexpr int WPB = BLOCK / kWave;
+    const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x % kWave;
+    const int64_t sl = (int64_t)b * WPB + w;
+    if (sl >= n_slices) return;  // whole wavefronts
+    const int64_t base = slice_ptr[sl];
+    const int32_t groups = (int32_t)((slice_ptr[sl + 1] - base) / (kSellSlice * kSellGroup));
+    const double acc = sell_row_sum<V, UNROLL, PIPE>(col, val, x, base, groups, 0, 1, lane);
+    const int64_t p = sl * kSellSlice + lane;
+    if (p < n_rows) store_y(y, PERM ? perm[p] : p, acc, alpha, beta);
+}
+
+template <class V, int KS, int UNROLL, bool PIPE, bool PERM>
+__global__ __launch_bounds__(KS * 64) void sell_ksplit_kernel(int32_t n_rows, int32_t n_slices,
+                                                              const int64_t *__restrict__ slice_ptr,
+                                                              const int32_t *__restrict__ perm,
+                                                              const int32_t *__restrict__ col,
+                                                              const V *__restrict__ val,
+                                                              const V *__restrict__ x, V alpha,
+                                                              V beta, V *__restrict__ y) {
+    __shared__ double s_acc[KS][kWave];
+    const int64_t sl = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x % kWave;
+    const int64_t base = slice_ptr[sl];
+    const int32_t groups = (int32_t)((slice_ptr[sl + 1] - base) / (kSellSlice * kSellGroup));
+    s_acc[w][lane] = sell_row_sum<V, UNROLL, PIPE>(col, val, x, base, groups, w, KS, lane);
+    __syncthreads();
+    if (w == 0) {
+        double t = s_acc[0][lane];
+#pragma unroll
+        for (int q = 1; q < KS; ++q) t += s_acc[q][lane];
+        const int64_t p = sl * kSellSlice + lane;
+        if (p < n_rows) store_y(y, PERM ? perm[p] : p, t, alpha, beta);
+    }
+}
+
+// ---- BELL: ELL over b x b blocks ---------------------------------------------------
+//
+// B / RB threads share a block row; thread j of them owns rows j * RB ... j * RB
+// + RB - 1 of it. Per slot it reads the block column (the same word for the
+// block row's threads), its RB x B values (contiguous: a wavefront streams
+// consecutive blocks) and the B consecutive x values of the block column with
+// one vector load where the block lies inside the matrix. UNROLL slots are
+// loaded before their products. Rows are summed in FP64 in block-column order.
+
+template <class V, int N>
+__device__ __forceinline__ void load_x_run(const V *__restrict__ x, int64_t c0, int32_t n_cols,
+                                           V (&xv)[N]) {
+    if (c0 + N <= n_cols) {
+        const Pack<V, N> p = ld_xrun<V, N>(x + c0);
+#pragma unroll
+        for (int j = 0; j < N; ++j) xv[j] = p.v[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j) xv[j] = (c0 + j < n_cols) ? x[c0 + j] : V(0);
+    }
+}
+
+template <class V, int B, int RB, int BLOCK, int UNROLL>
+__global__ __launch_bounds__(BLOCK) void bell_kernel(int32_t n_rows, int32_t n_cols, int32_t K,
+                                                     int32_t pitch, int32_t nbr,
+                                                     const int32_t *__restrict__ bcol,
+                                                     const V *__restrict__ bval,
+                                                     const V *__restrict__ x, V alpha, V beta,
+                                                     V *__restrict__ y) {
+    constexpr int TPB = B / RB;  // threads per block row
+    const int blk = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int64_t t = (int64_t)blk * BLOCK + threadIdx.x;
+    const int64_t br = t / TPB;
+    const int sub = (int)(t % TPB);
+    if (br >= nbr) return;
+    double acc[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) acc[i] = 0.0;
+    for (int32_t k = 0; k < K; k += UNROLL) {
+        int32_t bc[UNROLL];
+        Pack<V, RB * B> v[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const int32_t ku = k + u < K ? k + u : k;
+            const int64_t slot = (int64_t)ku * pitch + br;
+            bc[u] = k + u < K ? ld_stream(bcol + slot) : -1;
+            v[u] = ld_val<RB * B>(bval + (slot * B + sub * RB) * B);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            if (bc[u] < 0) continue;  // padding: no x is read
+            V xv[B];
+            load_x_run<V, B>(x, (int64_t)bc[u] * B, n_cols, xv);
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+#pragma unroll
+                for (int j = 0; j < B; ++j) acc[i] += (double)v[u].v[i * B + j] * (double)xv[j];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+        const int64_t r = br * B + sub * RB + i;
+        if (r < n_rows) store_y(y, r, acc[i], alpha, beta);
+    }
+}
+
 template <class V>
 __global__ __launch_bounds__(256) void scale_y(int32_t n, V beta, V *__restrict__ y) {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
@@ -795,6 +1032,68 @@ void hyb_sorted_launch(const Args &a) {
     hyb_sorted_tail(h, ITEMS, a.alpha, a.x, a.y, a.s);
 }
 
+template <class V, int BLOCK, int UNROLL, bool PIPE>
+void sell_launch(const Args &a) {
+    const spmv_matrix_s *h = a.h;
+    const SellPart &P = h->sell;
+    if (h->n_rows == 0 || P.n_slices == 0) return;
+    constexpr int WPB = BLOCK / kWave;
+    const int grid = grid_of(P.n_slices, WPB);
+    if (P.sigma > 1)
+        sell_kernel<V, BLOCK, UNROLL, PIPE, true><<<grid, BLOCK, 0, a.s>>>(
+            h->n_rows, P.n_slices, P.slice_ptr.as<int64_t>(), P.perm.as<int32_t>(),
+            P.col.as<int32_t>(), P.val.as<V>(), (const V *)a.x, (V)a.alpha, (V)a.beta, (V *)a.y);
+    else
+        sell_kernel<V, BLOCK, UNROLL, PIPE, false><<<grid, BLOCK, 0, a.s>>>(
+            h->n_rows, P.n_slices, P.slice_ptr.as<int64_t>(), nullptr, P.col.as<int32_t>(),
+            P.val.as<V>(), (const V *)a.x, (V)a.alpha, (V)a.beta, (V *)a.y);
+    SPMV_CHECK_LAUNCH();
+}
+
+template <class V, int KS, int UNROLL, bool PIPE>
+void sell_ksplit_launch(const Args &a) {
+    const spmv_matrix_s *h = a.h;
+    const SellPart &P = h->sell;
+    if (h->n_rows == 0 || P.n_slices == 0) return;
+    if (P.sigma > 1)
+        sell_ksplit_kernel<V, KS, UNROLL, PIPE, true><<<P.n_slices, KS * kWave, 0, a.s>>>(
+            h->n_rows, P.n_slices, P.slice_ptr.as<int64_t>(), P.perm.as<int32_t>(),
+            P.col.as<int32_t>(), P.val.as<V>(), (const V *)a.x, (V)a.alpha, (V)a.beta, (V *)a.y);
+    else
+        sell_ksplit_kernel<V, KS, UNROLL, PIPE, false><<<P.n_slices, KS * kWave, 0, a.s>>>(
+            h->n_rows, P.n_slices, P.slice_ptr.as<int64_t>(), nullptr, P.col.as<int32_t>(),
+            P.val.as<V>(), (const V *)a.x, (V)a.alpha, (V)a.beta, (V *)a.y);
+    SPMV_CHECK_LAUNCH();
+}
+
+template <class V, int B, int RB, int BLOCK, int UNROLL>
+void bell_launch_b(const Args &a) {
+    const spmv_matrix_s *h = a.h;
+    const BellPart &P = h->bell;
+    if constexpr (RB > B) {
+        fail(SPMV_ERR_NOT_APPLICABLE, "BELL variant with %d rows per thread on %dx%d blocks", RB, B, B);
+    } else {
+        const int64_t threads = (int64_t)P.n_block_rows * (B / RB);
+        bell_kernel<V, B, RB, BLOCK, UNROLL><<<grid_of(threads, BLOCK), BLOCK, 0, a.s>>>(
+            h->n_rows, h->n_cols, P.K, P.pitch, P.n_block_rows, P.col.as<int32_t>(), P.val.as<V>(),
+            (const V *)a.x, (V)a.alpha, (V)a.beta, (V *)a.y);
+        SPMV_CHECK_LAUNCH();
+    }
+}
+
+template <class V, int RB, int BLOCK, int UNROLL>
+void bell_launch(const Args &a) {
+    const spmv_matrix_s *h = a.h;
+    if (!h->bell.built) fail(SPMV_ERR_NOT_CONVERTED, "BELL not converted");
+    if (h->n_rows == 0) return;
+    switch (h->bell.b) {
+        case 2: bell_launch_b<V, 2, RB, BLOCK, UNROLL>(a); return;
+        case 4: bell_launch_b<V, 4, RB, BLOCK, UNROLL>(a); return;
+        case 8: bell_launch_b<V, 8, RB, BLOCK, UNROLL>(a); return;
+    }
+    fail(SPMV_ERR_INVALID_ARG, "BELL block size %d", h->bell.b);
+}
+
 #define V2(kind, blk, lanes, unr, fn) \
     Variant{{kind, blk, lanes, unr, 1, 0, 1}, fn<float>, fn<double>}
 #define V4(kind, blk, lanes, unr, fn) \
@@ -880,6 +1179,25 @@ template <class V> void hyb_s2_16(const Args &a) { hyb_sorted_launch<V, 2, 16>(a
 template <class V> void hyb_1_8(const Args &a) { hyb_launch<V, 1, 8>(a); }
 template <class V> void hyb_2_4(const Args &a) { hyb_launch<V, 2, 4>(a); }
 template <class V> void hyb_2_8(const Args &a) { hyb_launch<V, 2, 8>(a); }
+
+#define SELLV(B, U, P) \
+    template <class V> void sell_##B##_##U##_##P(const Args &a) { sell_launch<V, B, U, P>(a); }
+SELLV(256, 1, 0) SELLV(256, 2, 0) SELLV(256, 4, 0) SELLV(256, 1, 1) SELLV(256, 2, 1) SELLV(256, 4, 1)
+SELLV(64, 2, 0) SELLV(128, 2, 0) SELLV(512, 2, 0) SELLV(1024, 2, 0)
+#undef SELLV
+template <class V> void sell_k4(const Args &a) { sell_ksplit_launch<V, 4, 1, true>(a); }
+template <class V> void sell_k16(const Args &a) { sell_ksplit_launch<V, 16, 1, true>(a); }
+#define BELLV(R, B, U) \
+    template <class V> void bell_##R##_##B##_##U(const Args &a) { bell_launch<V, R, B, U>(a); }
+BELLV(1, 256, 1) BELLV(2, 256, 1) BELLV(4, 256, 1) BELLV(1, 256, 2) BELLV(2, 256, 2) BELLV(4, 256, 2)
+BELLV(1, 64, 1) BELLV(1, 128, 1) BELLV(1, 512, 1) BELLV(1, 1024, 1)
+BELLV(2, 64, 1) BELLV(2, 128, 1) BELLV(2, 512, 1) BELLV(2, 1024, 1)
+#undef BELLV
+
+#define VS(blk, unr, pipe, ks, fn) \
+    Variant{{SPMV_KERNEL_SELL, blk, 1, unr, 4, pipe, ks}, fn<float>, fn<double>}
+#define VB(blk, rb, unr, fn) \
+    Variant{{SPMV_KERNEL_BELL, blk, rb, unr, 0, 0, 1}, fn<float>, fn<double>}
 
 const std::vector<Variant> &table(spmv_format f) {
     static const std::vector<Variant> csr = {
@@ -971,12 +1289,29 @@ const std::vector<Variant> &table(spmv_format f) {
         Variant{{SPMV_KERNEL_HYB, 256, 2, 8, 2, 1, 1}, hyb_s2_8<float>, hyb_s2_8<double>},
         Variant{{SPMV_KERNEL_HYB, 256, 2, 16, 2, 1, 1}, hyb_s2_16<float>, hyb_s2_16<double>},
     };
+    static const std::vector<Variant> sell = {
+        VS(256, 1, 0, 1, sell_256_1_0), VS(256, 2, 0, 1, sell_256_2_0), VS(256, 4, 0, 1, sell_256_4_0),
+        VS(256, 1, 1, 1, sell_256_1_1), VS(256, 2, 1, 1, sell_256_2_1), VS(256, 4, 1, 1, sell_256_4_1),
+        VS(64, 2, 0, 1, sell_64_2_0), VS(128, 2, 0, 1, sell_128_2_0), VS(512, 2, 0, 1, sell_512_2_0),
+        VS(1024, 2, 0, 1, sell_1024_2_0),
+        VS(256, 1, 1, 4, sell_k4), VS(1024, 1, 1, 16, sell_k16),
+    };
+    static const std::vector<Variant> bell = {
+        VB(256, 1, 1, bell_1_256_1), VB(256, 2, 1, bell_2_256_1), VB(256, 4, 1, bell_4_256_1),
+        VB(256, 1, 2, bell_1_256_2), VB(256, 2, 2, bell_2_256_2), VB(256, 4, 2, bell_4_256_2),
+        VB(64, 1, 1, bell_1_64_1), VB(128, 1, 1, bell_1_128_1), VB(512, 1, 1, bell_1_512_1),
+        VB(1024, 1, 1, bell_1_1024_1),
+        VB(64, 2, 1, bell_2_64_1), VB(128, 2, 1, bell_2_128_1), VB(512, 2, 1, bell_2_512_1),
+        VB(1024, 2, 1, bell_2_1024_1),
+    };
     static const std::vector<Variant> none;
     switch (f) {
         case SPMV_FMT_CSR: return csr;
         case SPMV_FMT_COO: return coo;
         case SPMV_FMT_ELL: return ell;
         case SPMV_FMT_HYB: return hyb;
+        case SPMV_FMT_SELL: return sell;
+        case SPMV_FMT_BELL: return bell;
     }
     return none;
 }
@@ -1018,8 +1353,24 @@ int32_t default_variant(const spmv_matrix_s *h, spmv_format f) {
         case SPMV_FMT_COO: return 1;
         case SPMV_FMT_ELL: return 0;
         case SPMV_FMT_HYB: return 0;
+        case SPMV_FMT_SELL: return 1;  // two groups per step, 256 threads
+        case SPMV_FMT_BELL: {
+            // a whole 2 x 2 block per thread, one row of a larger block per thread
+            const int rb = (h->bell.built && h->bell.b == 2) ? 2 : 1;
+            const auto &t = table(f);
+            for (int32_t i = 0; i < (int32_t)t.size(); ++i)
+                if (t[i].info.lanes == rb && t[i].info.block == 256 && t[i].info.unroll == 1) return i;
+            return 0;
+        }
     }
     return 0;
+}
+
+bool variant_applicable(const spmv_matrix_s *h, spmv_format f, int32_t idx) {
+    const auto &t = table(f);
+    if (idx < 0 || idx >= (int32_t)t.size()) return false;
+    if (f == SPMV_FMT_BELL && h->bell.built) return t[idx].info.lanes <= h->bell.b;
+    return true;
 }
 
 bool variant_needs_panel(spmv_format f, int32_t idx) {

@@ -33,11 +33,12 @@ _lib = ctypes.CDLL(LIB_PATH)
 SPMV_OK = 0
 STATUS_NAMES = ("OK", "INVALID_ARG", "OUT_OF_BOUNDS", "DUPLICATE", "NOT_CONVERTED",
                 "NOT_APPLICABLE", "OOM", "HIP", "NO_MODEL")
-SPMV_FMT_CSR, SPMV_FMT_COO, SPMV_FMT_ELL, SPMV_FMT_HYB = 0, 1, 2, 3
-FORMAT_NAMES = ("CSR", "COO", "ELL", "HYB")
+SPMV_FMT_CSR, SPMV_FMT_COO, SPMV_FMT_ELL, SPMV_FMT_HYB, SPMV_FMT_SELL, SPMV_FMT_BELL = range(6)
+FORMAT_NAMES = ("CSR", "COO", "ELL", "HYB", "SELL", "BELL")
+SPMV_NUM_FORMATS = 6
 SPMV_F32, SPMV_F64 = 0, 1
 KERNEL_NAMES = ("csr_scalar", "csr_vector", "coo", "ell", "hyb", "coo_panel", "coo_sorted", "coo_split",
-                "csr_stream")
+                "csr_stream", "sell", "bell")
 SPMV_SELECT_MODEL, SPMV_SELECT_EXHAUSTIVE, SPMV_SELECT_RULE = 0, 1, 2
 
 
@@ -64,7 +65,9 @@ class spmv_arrays(ctypes.Structure):
                 ("row_ptr", ctypes.c_void_p), ("row", ctypes.c_void_p), ("col", ctypes.c_void_p),
                 ("val", ctypes.c_void_p), ("ell_col", ctypes.c_void_p),
                 ("ell_val", ctypes.c_void_p), ("tail_row", ctypes.c_void_p),
-                ("tail_col", ctypes.c_void_p), ("tail_val", ctypes.c_void_p)]
+                ("tail_col", ctypes.c_void_p), ("tail_val", ctypes.c_void_p),
+                ("sigma", ctypes.c_int32), ("n_slices", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("slots", ctypes.c_int64), ("slice_ptr", ctypes.c_void_p), ("perm", ctypes.c_void_p)]
 
 
 _P = ctypes.c_void_p
@@ -97,16 +100,29 @@ _sig("spmv_select_format", _I32, _P, _I32, ctypes.POINTER(_I32), _P, _P)
 class spmv_train_opts(ctypes.Structure):
     _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32),
                 ("max_steps", ctypes.c_int32), ("lr", ctypes.c_float), ("l2", ctypes.c_float),
-                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("classes", ctypes.c_int32)]
 
 
 SPMV_SELECTOR_PARAMS = 5252
 SPMV_SELECTOR_MODEL = 5276
+SPMV_SELECTOR_PARAMS6 = 5382
+SPMV_SELECTOR_MODEL6 = 5406
+_PARAMS_OF = {4: SPMV_SELECTOR_PARAMS, 6: SPMV_SELECTOR_PARAMS6}
+_MODEL_OF = {4: SPMV_SELECTOR_MODEL, 6: SPMV_SELECTOR_MODEL6}
 _sig("spmv_selector_train", _I32, _P, _P, _I32, _P, _P, ctypes.POINTER(spmv_train_opts), _P, _P, _P)
-_sig("spmv_selector_loss_grad", _I32, _P, _P, _P, _I32, _F, _P, _P, _P)
-_sig("spmv_selector_predict", _I32, _P, _P, _I32, _P, _P, _P, _P)
+_sig("spmv_selector_loss_grad", _I32, _P, _I32, _P, _P, _I32, _F, _P, _P, _P)
+_sig("spmv_selector_predict", _I32, _P, _I32, _P, _I32, _P, _P, _P, _P)
 _sig("spmv_selector_set_weights", _I32, _P, _I64)
 _sig("spmv_selector_get_weights", _I32, _P, _I64)
+_sig("spmv_selector_classes", _I32)
+
+
+def _classes_from(numel, table, name):
+    for c, n in table.items():
+        if int(numel) == n:
+            return c
+    raise ValueError(f"{name} has {numel} values; expected one of {sorted(table.values())}")
 _sig("spmv_status_string", ctypes.c_char_p, _I32)
 _sig("spmv_last_error", ctypes.c_char_p)
 
@@ -245,8 +261,9 @@ def spmv_destroy(h: Handle):
         h.ptr = None
 
 
-def spmv_convert(h: Handle, fmt: int, hyb_k: int = -1, stream=None):
-    _check(_lib.spmv_convert(h.ptr, int(fmt), int(hyb_k), _stream_ptr(stream)), "spmv_convert")
+def spmv_convert(h: Handle, fmt: int, param: int = -1, stream=None):
+    """Build a format; param: HYB width, SELL sigma, BELL block edge (-1: the rule)."""
+    _check(_lib.spmv_convert(h.ptr, int(fmt), int(param), _stream_ptr(stream)), "spmv_convert")
 
 
 def _device_buffer(a, name):
@@ -321,9 +338,9 @@ def spmv_features(h: Handle, stream=None) -> np.ndarray:
 
 
 def spmv_select_format(h: Handle, mode: int, stream=None):
-    """(format, scores[4]) chosen by MODEL / EXHAUSTIVE / RULE."""
+    """(format, scores[SPMV_NUM_FORMATS]) chosen by MODEL / EXHAUSTIVE / RULE."""
     f = _I32()
-    scores = np.zeros(4, dtype=np.float32)
+    scores = np.zeros(SPMV_NUM_FORMATS, dtype=np.float32)
     _check(_lib.spmv_select_format(h.ptr, int(mode), ctypes.byref(f),
                                    ctypes.c_void_p(scores.ctypes.data), _stream_ptr(stream)),
            "spmv_select_format")
@@ -344,13 +361,17 @@ def _dev_ptr(t, name, allow_none=False):
 def spmv_selector_train(feats, labels, init_params, perms, epochs=200, batch=200, lr=1e-3,
                         l2=1e-4, beta1=0.9, beta2=0.999, eps=1e-8, max_steps=0, out_model=None,
                         out_losses=None, stream=None):
-    """Train on the device; returns the model tensor (float32[5276] on the device)."""
+    """Train on the device; returns the model tensor (float32[5276] or [5406] on the device).
+    The class count (4 or 6) follows the size of init_params."""
     import torch
     n = int(feats.shape[0])
+    classes = _classes_from(init_params.numel(), _PARAMS_OF, "init_params")
     if out_model is None:
-        out_model = torch.empty(SPMV_SELECTOR_MODEL, dtype=torch.float32, device=feats.device)
+        out_model = torch.empty(_MODEL_OF[classes], dtype=torch.float32, device=feats.device)
+    elif out_model.numel() != _MODEL_OF[classes]:
+        raise ValueError(f"out_model must hold {_MODEL_OF[classes]} values")
     o = spmv_train_opts(int(epochs), int(batch), int(max_steps), float(lr), float(l2),
-                        float(beta1), float(beta2), float(eps))
+                        float(beta1), float(beta2), float(eps), classes)
     _check(_lib.spmv_selector_train(_dev_ptr(feats, "feats"), _dev_ptr(labels, "labels"), n,
                                      _dev_ptr(init_params, "init_params"), _dev_ptr(perms, "perms"),
                                      ctypes.byref(o), _dev_ptr(out_model, "out_model"),
@@ -360,11 +381,13 @@ def spmv_selector_train(feats, labels, init_params, perms, epochs=200, batch=200
 
 
 def spmv_selector_loss_grad(params, z, labels, l2=1e-4, stream=None):
-    """(loss tensor[1], grad tensor[5252]) of one minibatch, on the device."""
+    """(loss tensor[1], grad tensor[params]) of one minibatch, on the device; the class count
+    follows the size of params."""
     import torch
+    classes = _classes_from(params.numel(), _PARAMS_OF, "params")
     loss = torch.empty(1, dtype=torch.float32, device=z.device)
-    grad = torch.empty(SPMV_SELECTOR_PARAMS, dtype=torch.float32, device=z.device)
-    _check(_lib.spmv_selector_loss_grad(_dev_ptr(params, "params"), _dev_ptr(z, "z"),
+    grad = torch.empty(_PARAMS_OF[classes], dtype=torch.float32, device=z.device)
+    _check(_lib.spmv_selector_loss_grad(_dev_ptr(params, "params"), classes, _dev_ptr(z, "z"),
                                         _dev_ptr(labels, "labels"), int(z.shape[0]), float(l2),
                                         _dev_ptr(loss, "loss"), _dev_ptr(grad, "grad"),
                                         _stream_ptr(stream)), "spmv_selector_loss_grad")
@@ -372,12 +395,21 @@ def spmv_selector_loss_grad(params, z, labels, l2=1e-4, stream=None):
 
 
 def spmv_selector_predict(model, feats, applicable=None, stream=None):
-    """(logits[n][4], cls[n]) device tensors; model None = the weights set on this device."""
+    """(logits[n][C], cls[n]) device tensors; model None = the weights set on this device."""
     import torch
     n = int(feats.shape[0])
-    logits = torch.empty((n, 4), dtype=torch.float32, device=feats.device)
+    if model is None:
+        classes = int(_lib.spmv_selector_classes())
+        if classes == 0:
+            raise SpmvError(8, "spmv_selector_predict")
+    else:
+        classes = _classes_from(model.numel(), _MODEL_OF, "model")
+    if applicable is not None and tuple(applicable.shape) != (n, classes):
+        raise ValueError(f"applicable must be [{n}][{classes}]")
+    logits = torch.empty((n, classes), dtype=torch.float32, device=feats.device)
     cls = torch.empty(n, dtype=torch.int32, device=feats.device)
-    _check(_lib.spmv_selector_predict(_dev_ptr(model, "model", True), _dev_ptr(feats, "feats"), n,
+    _check(_lib.spmv_selector_predict(_dev_ptr(model, "model", True), classes if model is not None else 0,
+                                      _dev_ptr(feats, "feats"), n,
                                       _dev_ptr(applicable, "applicable", True),
                                       _dev_ptr(logits, "logits"), _dev_ptr(cls, "cls"),
                                       _stream_ptr(stream)), "spmv_selector_predict")
@@ -385,7 +417,8 @@ def spmv_selector_predict(model, feats, applicable=None, stream=None):
 
 
 def spmv_selector_set_weights(params):
-    """Install a 5276-float model on the current device; None forgets it."""
+    """Install a 5276-float (4 classes) or 5406-float (6 classes) model on the current
+    device; None forgets it."""
     if params is None:
         _check(_lib.spmv_selector_set_weights(ctypes.c_void_p(0), 0), "spmv_selector_set_weights")
         return
@@ -394,8 +427,14 @@ def spmv_selector_set_weights(params):
            "spmv_selector_set_weights")
 
 
+def spmv_selector_classes() -> int:
+    """Classes of the network installed on the current device (0: none)."""
+    return int(_lib.spmv_selector_classes())
+
+
 def spmv_selector_get_weights() -> np.ndarray:
-    out = np.zeros(SPMV_SELECTOR_MODEL, dtype=np.float32)
+    classes = spmv_selector_classes()
+    out = np.zeros(_MODEL_OF.get(classes, SPMV_SELECTOR_MODEL), dtype=np.float32)
     _check(_lib.spmv_selector_get_weights(ctypes.c_void_p(out.ctypes.data), out.size),
            "spmv_selector_get_weights")
     return out
@@ -555,6 +594,17 @@ def arrays_to_host(h: Handle, fmt: int) -> dict:
         out["row"] = device_tensor(v.row, h.nnz, np.int32).cpu().numpy()
         out["col"] = device_tensor(v.col, h.nnz, np.int32).cpu().numpy()
         out["val"] = device_tensor(v.val, h.nnz, vd).cpu().numpy()
+    elif fmt == SPMV_FMT_SELL:
+        out.update(sigma=v.sigma, n_slices=v.n_slices, slots=v.slots)
+        out["slice_ptr"] = device_tensor(v.slice_ptr, v.n_slices + 1, np.int64).cpu().numpy()
+        out["perm"] = (device_tensor(v.perm, h.n_rows, np.int32).cpu().numpy() if v.perm
+                       else np.arange(h.n_rows, dtype=np.int32))
+        out["col"] = device_tensor(v.ell_col, v.slots, np.int32).cpu().numpy()
+        out["val"] = device_tensor(v.ell_val, v.slots, vd).cpu().numpy()
+    elif fmt == SPMV_FMT_BELL:
+        out.update(b=v.block)
+        out["bcol"] = device_tensor(v.ell_col, v.slots, np.int32).cpu().numpy()
+        out["bval"] = device_tensor(v.ell_val, v.slots * v.block * v.block, vd).cpu().numpy()
     else:
         n = v.K * v.pitch
         out["ell_col"] = device_tensor(v.ell_col, n, np.int32).cpu().numpy()

@@ -3,9 +3,9 @@
 Both the GPU trainer and the oracle take these as inputs, so neither draws
 random numbers of its own.
 
-Flat parameter layout (float32, 5,252 values), for layer sizes 12-64-64-4:
-W1[64][12], b1[64], W2[64][64], b2[64], W3[4][64], b3[4]; each W is stored
-row-major as [out][in].
+Flat parameter layout (float32), for layer sizes 12-64-64-C: W1[64][12], b1[64],
+W2[64][64], b2[64], W3[C][64], b3[C]; each W is stored row-major as [out][in]
+(5,252 values for C = 4, 5,382 for C = 6).
 """
 from __future__ import annotations
 

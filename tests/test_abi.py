@@ -20,12 +20,14 @@ def test_every_declared_function_is_exported_and_bound():
 
 
 def test_variant_catalogue():
-    for fmt in range(4):
+    for fmt in range(6):
         for dt in (S.SPMV_F32, S.SPMV_F64):
             n = S.spmv_variant_count(fmt, dt)
             assert n >= 3
             kinds = {S.spmv_variant_describe(fmt, dt, i)["kernel"] for i in range(n)}
-            want = {0: {"csr_scalar", "csr_vector", "csr_stream"}, 1: {"coo", "coo_panel", "coo_sorted", "coo_split"}, 2: {"ell"}, 3: {"hyb"}}[fmt]
+            want = {0: {"csr_scalar", "csr_vector", "csr_stream"},
+                    1: {"coo", "coo_panel", "coo_sorted", "coo_split"}, 2: {"ell"}, 3: {"hyb"},
+                    4: {"sell"}, 5: {"bell"}}[fmt]
             assert kinds == want
             with pytest.raises(S.SpmvError) as e:
                 S.spmv_variant_describe(fmt, dt, n)

@@ -91,6 +91,49 @@ def test_ell_and_hyb(name, dtype):
             assert _same_bits(g[key], hy[key]), (k, key)
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("name", list(C.CASES))
+def test_sell_and_bell(name, dtype):
+    """SELL (sigma by the rule, 1, 128, 16384) and BELL (size by the rule, 2, 4, 8): every
+    array bit-equal to the oracle's layout, or NOT_APPLICABLE where the oracle refuses."""
+    print(f"[convert sell/bell] {name} {dtype.__name__}", flush=True)
+    h = _create(name, dtype)
+    ref = C.canonical(name, dtype)
+    for sigma in (-1, 1, 128, 16384):
+        try:
+            want = OF.to_sell(ref, sigma)
+        except OF.OracleError as err:
+            assert err.status == OF.NOT_APPLICABLE
+            with pytest.raises(S.SpmvError) as got:
+                S.spmv_convert(h, S.SPMV_FMT_SELL, sigma)
+            assert got.value.status == "NOT_APPLICABLE"
+            continue
+        S.spmv_convert(h, S.SPMV_FMT_SELL, sigma)
+        g = S.arrays_to_host(h, S.SPMV_FMT_SELL)
+        assert (g["sigma"], g["n_slices"], g["slots"]) == \
+            (want["sigma"], want["n_slices"], int(want["slice_ptr"][-1])), sigma
+        assert np.array_equal(g["slice_ptr"], want["slice_ptr"]), sigma
+        assert np.array_equal(g["perm"], want["perm"]), sigma
+        assert _same_bits(g["col"], want["col"]) and _same_bits(g["val"], want["val"]), sigma
+    for b in (-1, 2, 4, 8):
+        try:
+            want = OF.to_bell(ref, b)
+        except OF.OracleError as err:
+            assert err.status == OF.NOT_APPLICABLE
+            with pytest.raises(S.SpmvError) as got:
+                S.spmv_convert(h, S.SPMV_FMT_BELL, b)
+            assert got.value.status == "NOT_APPLICABLE"
+            continue
+        S.spmv_convert(h, S.SPMV_FMT_BELL, b)
+        g = S.arrays_to_host(h, S.SPMV_FMT_BELL)
+        assert (g["b"], g["K"], g["pitch"]) == (want["b"], want["K"], want["pitch"]), b
+        assert _same_bits(g["bcol"], want["bcol"]) and _same_bits(g["bval"], want["bval"]), b
+    for bad in ((S.SPMV_FMT_SELL, 0), (S.SPMV_FMT_SELL, 100), (S.SPMV_FMT_BELL, 3), (S.SPMV_FMT_BELL, 16)):
+        with pytest.raises(S.SpmvError) as got:
+            S.spmv_convert(h, *bad)
+        assert got.value.status == "INVALID_ARG"
+
+
 def test_input_errors():
     def status(*args, **kw):
         with pytest.raises(S.SpmvError) as e:

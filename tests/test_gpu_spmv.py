@@ -20,7 +20,8 @@ torch = pytest.importorskip("torch")
 import paper_2302_05662_amd as S  # noqa: E402
 
 DTYPES = [np.float32, np.float64]
-FORMATS = [S.SPMV_FMT_CSR, S.SPMV_FMT_COO, S.SPMV_FMT_ELL, S.SPMV_FMT_HYB]
+FORMATS = [S.SPMV_FMT_CSR, S.SPMV_FMT_COO, S.SPMV_FMT_ELL, S.SPMV_FMT_HYB, S.SPMV_FMT_SELL,
+           S.SPMV_FMT_BELL]
 
 
 def _create(name, dtype):
@@ -42,15 +43,21 @@ def _set_variant(h, fmt, var):
 
 
 def _formats_for(h, name, dtype):
+    """Every format the oracle says applies, converted on h (SELL and BELL by their rules)."""
     out = [S.SPMV_FMT_CSR, S.SPMV_FMT_COO]
-    try:
-        OF.to_ell(C.canonical(name, dtype))
-        S.spmv_convert(h, S.SPMV_FMT_ELL)
-        out.append(S.SPMV_FMT_ELL)
-    except OF.OracleError:
-        pass
-    S.spmv_convert(h, S.SPMV_FMT_HYB)
-    out.append(S.SPMV_FMT_HYB)
+    ref = C.canonical(name, dtype)
+    for fmt, build in ((S.SPMV_FMT_ELL, OF.to_ell), (S.SPMV_FMT_HYB, OF.to_hyb),
+                       (S.SPMV_FMT_SELL, OF.to_sell), (S.SPMV_FMT_BELL, OF.to_bell)):
+        try:
+            build(ref)
+        except OF.OracleError as e:
+            assert e.status == OF.NOT_APPLICABLE
+            with pytest.raises(S.SpmvError) as got:
+                S.spmv_convert(h, fmt)
+            assert got.value.status == "NOT_APPLICABLE", (name, S.FORMAT_NAMES[fmt])
+            continue
+        S.spmv_convert(h, fmt)
+        out.append(fmt)
     return out
 
 
@@ -78,6 +85,49 @@ def test_every_variant_matches_oracle(name, dtype):
         err = OS.max_row_error(yd.cpu().numpy(), y_ref, den)
         assert err <= tol, (S.FORMAT_NAMES[fmt], S.spmv_variant_describe(fmt, h.dtype_code, var), a, b, err)
     assert m.n_rows == 0 or runs
+
+
+SELL_BELL_CASES = ["random", "powerlaw", "banded", "blockdiag", "stencil", "wide", "tall",
+                   "one_long_row", "last_row_only", "single", "empty", "lap64"]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("name", SELL_BELL_CASES)
+def test_sell_and_bell_layouts_every_variant(name, dtype):
+    """SELL at sigma 1, 128 and 16384 and BELL at 2, 4 and 8: every variant, every (alpha, beta)."""
+    print(f"[spmv sell/bell] {name} {dtype.__name__}", flush=True)
+    m = C.matrix(name)
+    h = _create(name, dtype)
+    ref = C.canonical(name, dtype)
+    x, y0 = C.vectors(name, dtype)
+    xd = torch.from_numpy(x).cuda()
+    tol = C.TOL[dtype]
+    layouts = [(S.SPMV_FMT_SELL, p, OF.to_sell) for p in (1, 128, 16384)] + \
+              [(S.SPMV_FMT_BELL, p, OF.to_bell) for p in (2, 4, 8)]
+    ran = 0
+    for fmt, param, build in layouts:
+        try:
+            build(ref, param)
+        except OF.OracleError as e:
+            assert e.status == OF.NOT_APPLICABLE
+            with pytest.raises(S.SpmvError) as got:
+                S.spmv_convert(h, fmt, param)
+            assert got.value.status == "NOT_APPLICABLE"
+            continue
+        S.spmv_convert(h, fmt, param)
+        for var in range(S.spmv_variant_count(fmt, h.dtype_code)):
+            if not _set_variant(h, fmt, var):
+                d = S.spmv_variant_describe(fmt, h.dtype_code, var)
+                assert fmt == S.SPMV_FMT_BELL and d["lanes"] > param  # more rows than the block
+                continue
+            for a, b in C.ALPHA_BETA:
+                yd = torch.from_numpy(y0.copy()).cuda()
+                S.spmv_run(h, fmt, a, xd, b, yd)
+                y_ref, den = C.reference(name, dtype, a, b)
+                err = OS.max_row_error(yd.cpu().numpy(), y_ref, den)
+                assert err <= tol, (S.FORMAT_NAMES[fmt], param, var, a, b, err)
+                ran += 1
+    assert ran > 0 or m.nnz == 0 or m.n_rows == 0
 
 
 def test_laplacian_integer_closed_form_bit_exact():

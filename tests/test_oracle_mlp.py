@@ -174,3 +174,34 @@ def test_labels_and_regret():
     t = np.array([[1.0, 2.0, np.inf, 1.0], [3.0, 1.5, 1.2, 4.0]])
     assert M.labels_from_times(t).tolist() == [0, 2]
     assert M.regret(t, [3, 1]).tolist() == [0.0, 0.25]
+
+
+def test_six_class_layout_and_gradient():
+    # the network with SELL and BELL classes: 12-64-64-6, 5382 parameters
+    p = synth.glorot_params(21, layers=(12, 64, 64, 6)).astype(np.float64)
+    assert p.size == M.n_params(6) == 12 * 64 + 64 + 64 * 64 + 64 + 6 * 64 + 6 == 5382
+    assert M.classes_of(p) == 6 and M.classes_of(synth.glorot_params(0)) == 4
+    (W1, _), _, (W3, b3) = M.unpack(p)
+    assert W3.shape == (6, 64) and b3.shape == (6,)
+    # the first layers draw the same numbers as the 4-class network of the same seed
+    assert np.array_equal(W1, M.unpack(synth.glorot_params(21))[0][0])
+    rng = np.random.default_rng(22)
+    Z = rng.standard_normal((9, 12))
+    y = rng.integers(0, 6, 9)
+    p[4928:4992] = rng.uniform(-0.1, 0.1, 64)
+    loss, g = M.loss_and_grad(p, Z, y, 1e-3)
+    P = M.softmax(M.forward(p, Z)["logits"])
+    assert P.shape == (9, 6)
+    assert np.allclose(g[5376:5382], (P - np.eye(6)[y]).mean(axis=0), rtol=0, atol=1e-15)
+    h = 1e-6
+    for k in np.concatenate([rng.choice(5382, 200, replace=False), np.arange(4992, 5382, 7)]):
+        tp, tm = p.copy(), p.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (M.loss_and_grad(tp, Z, y, 1e-3)[0] - M.loss_and_grad(tm, Z, y, 1e-3)[0]) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-7 + 1e-5 * abs(g[k]), k
+    theta = np.zeros(5382)
+    theta[5376 + 5] = 1.0  # b3[BELL]
+    pred, _ = M.predict(theta, np.zeros(12), np.ones(12), np.ones((2, 12)),
+                        applicable=np.array([[True] * 6, [True] * 5 + [False]]))
+    assert pred.tolist() == [5, 0]
