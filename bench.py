@@ -31,7 +31,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 METRIC = "SpMV effective HBM GB/s (% of peak) per format; selector regret vs exhaustive"
-FMT_NAMES = ("CSR", "COO", "ELL", "HYB")
+FMT_NAMES = ("CSR", "COO", "ELL", "HYB", "SELL", "BELL")
+NF = len(FMT_NAMES)
+NF4 = 4  # the selector network's classes of the spec formats: CSR, COO, ELL, HYB
 
 
 def format_bytes(fmt, n_rows, n_cols, nnz, vb, K=0, pitch=0, tail=0):
@@ -78,6 +80,14 @@ def kernel_symbols(fmt, info, dtype="float"):
         return [f"csr_pipe_kernel<{dtype}, {b}, {l}, {pp}>"]
     if info["kernel"] == "ell" and info.get("ksplit", 1) > 1:
         return [f"ell_ksplit_kernel<{dtype}, {info['ksplit']}, {l}>"]
+    if info["kernel"] == "sell":
+        tf = "true" if pp else "false"
+        if info.get("ksplit", 1) > 1:
+            return [f"sell_ksplit_kernel<{dtype}, {info['ksplit']}, {u}, {tf}, "]
+        return [f"sell_kernel<{dtype}, {b}, {u}, {tf}, "]
+    if info["kernel"] == "bell":
+        # the block edge (second template argument) is the matrix's layout
+        return [f"bell_kernel<{dtype}, "]
     if info["kernel"] == "ell" and pp:
         return [f"ell_pipe_kernel<{dtype}, {b}, {l}, {pp}>"]
     if info["kernel"] == "csr_vector":
@@ -175,34 +185,51 @@ def counter_summary(fetch_csv, write_csv, bench_json, out_json):
     print(f"| traffic / algorithmic | {traffic / rf['bytes_per_launch']:.3f} |")
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(mats, budget_s, threads):
-    """The FP64 oracle's CSR SpMV on the host, over the first matrices until the budget is used."""
+    """The FP64 oracle's CSR SpMV on the host, over the first matrices until the budget is used.
+
+    The oracle's output for each timed matrix is also compared row by row with the y the
+    GPU left in the timed steps (y = A x, FP32 bound 1e-5); a miss ends the run with an error.
+    """
     from oracle import spmv as OS
 
-    done_bytes, done_t, names = 0.0, 0.0, []
+    names, checked, worst = [], 0, 0.0
     for m in mats:
-        if done_t >= budget_s:
+        if sum(t for _, t in names) * 5 >= budget_s:
             break
         rp = np.zeros(m["n_rows"] + 1, np.int64)
         np.cumsum(np.bincount(m["row"], minlength=m["n_rows"]), out=rp[1:])
         val = m["val"].astype(np.float64)
         x = m["x"].astype(np.float64)
         ts = []
-        for _ in range(3):
+        for _ in range(5):
             t0 = time.perf_counter()
-            OS.spmv_csr(rp, m["col"], val, x, 1.0, 0.0, None, n_threads=threads)
+            y_ref = OS.spmv_csr(rp, m["col"], val, x, 1.0, 0.0, None, n_threads=threads)
             ts.append(time.perf_counter() - t0)
-        done_t += sum(ts)
-        done_bytes += m["useful_bytes"]
-        done_t_med = float(np.median(ts))
-        names.append((m["name"], done_t_med))
+        names.append((m["name"], float(np.median(ts))))
+        den = OS.spmv_csr(rp, m["col"], np.abs(val), np.abs(x), 1.0, 0.0, None, n_threads=threads)
+        err = OS.max_row_error(m["y_gpu"], y_ref, den)
+        worst = max(worst, err)
+        checked += 1
+        if not err <= 1e-5:
+            raise SystemExit(f"{m['name']}: GPU y differs from the oracle (row error {err:.3g} > 1e-5)")
     if not names:
         return None
     tot_t = sum(t for _, t in names)
     tot_b = sum(mm["useful_bytes"] for mm in mats[:len(names)])
-    # one thread on the first two matrices, for scale
     one_b, one_t = 0.0, 0.0
-    for m in mats[:2]:
+    for m in mats[:2]:  # one thread on the first two matrices, for scale
         rp = np.zeros(m["n_rows"] + 1, np.int64)
         np.cumsum(np.bincount(m["row"], minlength=m["n_rows"]), out=rp[1:])
         val, x = m["val"].astype(np.float64), m["x"].astype(np.float64)
@@ -211,12 +238,14 @@ def cpu_baseline(mats, budget_s, threads):
         one_t += time.perf_counter() - t0
         one_b += m["useful_bytes"]
     return {"value": round(tot_b / tot_t / 1e9, 3), "unit": "GB/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "gflops": round(2 * sum(mm["nnz"] for mm in mats[:len(names)]) / tot_t / 1e9, 3),
             "single_thread_value": round(one_b / one_t / 1e9, 3),
+            "checked_matrices": checked, "max_row_error_vs_gpu": float(f"{worst:.3g}"),
             "sample": f"first {len(names)} of {len(mats)} matrices, FP64 CSR loop (FP32 inputs "
-                      f"promoted), median of 3 runs each, same useful-byte formula; "
-                      f"single_thread_value: first 2 matrices, one run each, 1 thread"}
+                      f"promoted) on {threads} threads (the CPU share of this process), median "
+                      f"of 5 runs each, same useful-byte formula; single_thread_value: first 2 "
+                      f"matrices, one run each, 1 thread"}
 
 
 def total_nnz_of(mats):
@@ -224,33 +253,27 @@ def total_nnz_of(mats):
 
 
 MODEL_PATH = os.path.join(ROOT, "paper_2302_05662_amd", "selector_model.npy")
+MODEL6_PATH = os.path.join(ROOT, "paper_2302_05662_amd", "selector_model6.npy")
 
 
 def selector_section(S, torch, mats, step, steps):
-    """Regret of the learned, rule and always-CSR choices against exhaustive timing."""
-    def regret(key):
-        r = [e["times"][e[key]] / e["times"][e["fmt"]] - 1.0 for e in mats]
+    """Regret of the learned, rule and always-CSR choices against exhaustive timing.
+
+    The 4-class network (CSR, COO, ELL, HYB) is scored against the best of those four
+    formats; the 6-class network, when present, against the best of all six.
+    """
+    def regret(key, best):
+        r = [e["times"][e[key]] / e["times"][e[best]] - 1.0 for e in mats]
         return {"mean": round(float(np.mean(r)), 4), "p95": round(float(np.percentile(r, 95)), 4),
                 "max": round(float(np.max(r)), 4),
                 "within_5pct": round(float(np.mean(np.array(r) <= 0.05)), 4),
                 "sum_time_ratio": round(sum(e["times"][e[key]] for e in mats)
-                                        / sum(e["times"][e["fmt"]] for e in mats) - 1.0, 4)}
+                                        / sum(e["times"][e[best]] for e in mats) - 1.0, 4)}
     for e in mats:
         e["csr"] = 0
         e["rule"] = S.spmv_select_format(e["h"], S.SPMV_SELECT_RULE)[0]
-    out = {"labels": "exhaustive autotuned cold medians (setup)", "always_csr": regret("csr"),
-           "rule": regret("rule"), "model": None}
-    if not os.path.exists(MODEL_PATH):
-        return out
-    S.spmv_selector_set_weights(np.load(MODEL_PATH))
-    lat = []
-    for e in mats:
-        t = time.perf_counter()
-        e["mlp"] = S.spmv_select_format(e["h"], S.SPMV_SELECT_MODEL)[0]
-        lat.append(time.perf_counter() - t)
-    model = regret("mlp")
-    model["accuracy"] = round(float(np.mean([e["mlp"] == e["fmt"] for e in mats])), 4)
-    model["select_ms_mean"] = round(1e3 * float(np.mean(lat)), 3)
+    out = {"labels": "exhaustive autotuned cold medians (setup)", "always_csr": regret("csr", "fmt4"),
+           "rule": regret("rule", "fmt4"), "model": None, "model6": None}
 
     def timed(key):
         for _ in range(2):
@@ -262,11 +285,26 @@ def selector_section(S, torch, mats, step, steps):
         torch.cuda.synchronize()
         return (time.perf_counter() - t) * 1e3 / steps
 
-    ms_best, ms_mlp = timed("fmt"), timed("mlp")
-    model["step_ms_exhaustive_plan"] = round(ms_best, 4)
-    model["step_ms_model_plan"] = round(ms_mlp, 4)
-    model["step_regret"] = round(ms_mlp / ms_best - 1.0, 4)
-    out["model"] = model
+    for path, key, best, name in ((MODEL_PATH, "mlp", "fmt4", "model"),
+                                  (MODEL6_PATH, "mlp6", "fmt", "model6")):
+        if not os.path.exists(path):
+            continue
+        S.spmv_selector_set_weights(np.load(path))
+        lat = []
+        for e in mats:
+            t = time.perf_counter()
+            e[key] = S.spmv_select_format(e["h"], S.SPMV_SELECT_MODEL)[0]
+            lat.append(time.perf_counter() - t)
+        model = regret(key, best)
+        model["classes"] = S.spmv_selector_classes()
+        model["accuracy"] = round(float(np.mean([e[key] == e[best] for e in mats])), 4)
+        model["select_ms_mean"] = round(1e3 * float(np.mean(lat)), 3)
+        ms_best, ms_mlp = timed(best), timed(key)
+        model[f"step_ms_exhaustive_plan"] = round(ms_best, 4)
+        model["step_ms_model_plan"] = round(ms_mlp, 4)
+        model["step_regret"] = round(ms_mlp / ms_best - 1.0, 4)
+        out[name] = model
+    S.spmv_selector_set_weights(None)
     return out
 
 
@@ -291,7 +329,7 @@ def ingest_unsorted(S, torch, synth, tune=True):
     y = torch.zeros(m.n_rows, dtype=torch.float32, device="cuda")
     useful = format_bytes(0, m.n_rows, m.n_cols, m.nnz, 4)
     per = {}
-    for fmt in range(4):
+    for fmt in range(NF):
         try:
             S.spmv_convert(h, fmt)
         except S.SpmvError as e:
@@ -334,7 +372,7 @@ def fp64_section(S, torch, synth, seeds):
         y = torch.zeros(m.n_rows, dtype=torch.float64, device="cuda")
         useful = format_bytes(0, m.n_rows, m.n_cols, m.nnz, 8)
         best, best_fmt = float("inf"), None
-        for fmt in range(4):
+        for fmt in range(NF):
             try:
                 S.spmv_convert(h, fmt)
             except S.SpmvError as e:
@@ -491,51 +529,55 @@ def main():
         yd = torch.zeros(m.n_rows, dtype=torch.float32, device="cuda")
         entry = {"name": m.name, "family": m.family, "n_rows": m.n_rows, "n_cols": m.n_cols,
                  "nnz": m.nnz, "h": h, "xd": xd, "y": yd, "times": {}, "variant": {}, "bytes": {},
-                 "feats": feats, "t_ingest": t_ingest, "t_feat": t_feat}
-        t = time.perf_counter()
-        try:
-            S.spmv_convert(h, S.SPMV_FMT_ELL)
-        except S.SpmvError as e:
-            if e.status != "NOT_APPLICABLE":
-                raise
-        entry["t_ell"] = time.perf_counter() - t
-        t = time.perf_counter()
-        S.spmv_convert(h, S.SPMV_FMT_HYB)
-        entry["t_hyb"] = time.perf_counter() - t
-        for fmt in range(4):
+                 "default_ms": {}, "feats": feats, "t_ingest": t_ingest, "t_feat": t_feat,
+                 "t_convert": {}}
+        xy = 4 * (m.n_rows + m.n_cols)
+        for fmt in range(NF):
+            t = time.perf_counter()
             try:
-                view = S.spmv_get_arrays(h, fmt)
-            except S.SpmvError:
+                S.spmv_convert(h, fmt)
+            except S.SpmvError as e:
+                if e.status != "NOT_APPLICABLE":
+                    raise
                 entry["times"][fmt] = float("inf")
                 continue
-            entry["bytes"][fmt] = format_bytes(fmt, m.n_rows, m.n_cols, m.nnz, 4, view.K, view.pitch,
-                                               view.nnz_tail)
+            entry["t_convert"][fmt] = time.perf_counter() - t
             if plan is not None:
                 pm = plan[m.name]
                 entry["times"][fmt] = pm["times"][fmt] if pm["times"][fmt] is not None else float("inf")
                 entry["variant"][fmt] = pm["variants"][fmt]
                 S.spmv_set_variant(h, fmt, pm["variants"][fmt])
-                continue
-            var, ms = S.spmv_tune(h, fmt, xd, yd, reps=args.tune_reps, flush=True)
-            entry["times"][fmt] = ms
-            entry["variant"][fmt] = var
-        if entry["variant"].get(1, -1) >= 0 and \
-                S.spmv_variant_describe(1, S.SPMV_F32, entry["variant"][1])["kernel"] in (
-                    "coo_panel", "coo_sorted"):
-            # the reordered COO copies keep one index per entry (row packed with the column,
-            # or the column with a 16-bit row beside it in tall sorted blocks) plus one
-            # pointer per row group or block, priced like CSR (an underestimate: the
-            # padding and the 16-bit rows are not counted)
-            entry["bytes"][1] = format_bytes(0, m.n_rows, m.n_cols, m.nnz, 4)
-        for fmt in range(4):
+            else:
+                # the default variant (the library's choice from the row lengths) before tuning:
+                # the tuned-over-default gain is the compile-time mode's result here
+                dv = S.spmv_get_variant(h, fmt)
+                entry["default_ms"][fmt] = float(np.median(S.spmv_time(
+                    h, fmt, xd, yd, variant=dv, warmup=1, reps=args.tune_reps, flush=True)))
+                var, ms = S.spmv_tune(h, fmt, xd, yd, reps=args.tune_reps, flush=True)
+                entry["times"][fmt] = ms
+                entry["variant"][fmt] = var
+            # bytes as stored: the layout the chosen variant streams, x once, y once
+            entry["bytes"][fmt] = S.spmv_stored_bytes(h, fmt) + xy
+        if plan is None:
+            # the tiled segmented COO kernel on its own (the sorted-block COO kernels read a
+            # reordered copy): its best variant's cold median, priced at nnz * 12 + x + y
+            tiled = [var for var in range(S.spmv_variant_count(S.SPMV_FMT_COO, S.SPMV_F32))
+                     if S.spmv_variant_describe(S.SPMV_FMT_COO, S.SPMV_F32, var)["kernel"] == "coo"]
+            entry["coo_tiled_ms"] = min(float(np.median(S.spmv_time(
+                h, S.SPMV_FMT_COO, xd, yd, variant=var, warmup=1, reps=args.tune_reps, flush=True)))
+                for var in tiled)
+            entry["coo_tiled_bytes"] = m.nnz * 12 + xy
+            S.spmv_set_variant(h, S.SPMV_FMT_COO, entry["variant"][S.SPMV_FMT_COO])
+        for fmt in range(NF):
             entry["variant"].setdefault(fmt, -1)
-        entry["fmt"] = int(np.argmin([entry["times"][f] for f in range(4)]))
-        entry["useful_bytes"] = entry["bytes"][0]
+        entry["fmt"] = int(np.argmin([entry["times"][f] for f in range(NF)]))
+        entry["fmt4"] = int(np.argmin([entry["times"][f] for f in range(NF4)]))
+        entry["useful_bytes"] = format_bytes(0, m.n_rows, m.n_cols, m.nnz, 4)
         if not args.no_cpu:
             entry.update(row=m.row, col=m.col, val=v, x=x)  # host copies for the CPU baseline
         mats.append(entry)
         print(f"[setup] {m.name}: nnz={m.nnz} best={FMT_NAMES[entry['fmt']]} "
-              f"ms={[round(entry['times'][f], 4) for f in range(4)]}", file=sys.stderr, flush=True)
+              f"ms={[round(entry['times'][f], 4) for f in range(NF)]}", file=sys.stderr, flush=True)
     setup_s = time.perf_counter() - t_setup
 
     def step(events=None, key="fmt"):
@@ -554,8 +596,10 @@ def main():
     setup_rates = {
         "ingest_nnz_per_s": round(total_nnz_of(mats) / sum(e["t_ingest"] for e in mats), 0),
         "features_nnz_per_s": round(total_nnz_of(mats) / sum(e["t_feat"] for e in mats), 0),
-        "convert_ell_hyb_nnz_per_s": round(
-            2 * total_nnz_of(mats) / sum(e["t_ell"] + e["t_hyb"] for e in mats), 0),
+        "convert_nnz_per_s": {FMT_NAMES[f]: round(
+            sum(e["nnz"] for e in mats if f in e["t_convert"])
+            / max(sum(e["t_convert"][f] for e in mats if f in e["t_convert"]), 1e-12), 0)
+            for f in range(2, NF)},
         "note": "host wall clock around each synchronous call, COO already in HBM; the paper's "
                 "CPU figures are about 4.8e5 (features) and 4.3e5 (conversion) nnz/s",
     }
@@ -591,6 +635,10 @@ def main():
                  "mean_ms": round(float(cold.mean(axis=1).sum()), 4),
                  "p95_ms": round(float(np.percentile(cold, 95, axis=1).sum()), 4)}
     cold_plan["useful_gbps_median"] = round(useful_all / (cold_plan["median_ms"] * 1e-3) / 1e9, 1)
+    cold_plan["frac_of_peak_median"] = round(cold_plan["useful_gbps_median"] / HBM_PEAK_GBPS, 4)
+    cold_plan["stored_gbps_median"] = round(
+        sum(e["bytes"][e["fmt"]] for e in mats) / (cold_plan["median_ms"] * 1e-3) / 1e9, 1)
+    cold_med = {id(e): float(np.median(cold[i])) for i, e in enumerate(mats)}
 
     # Warmup steps carry a pair of events on every launch: they give the kernel time per
     # step and pick the roofline kernel, the (format, variant) group with the largest
@@ -665,34 +713,79 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     ms_per_step = wall * 1e3 / args.steps
+    for e in mats:  # outputs of the last timed step, for the CPU leg's check
+        e["y_gpu"] = e["y"].cpu().numpy()
 
     useful = sum(e["useful_bytes"] for e in mats)
+    cold_dom_ms = sum(cold_med[id(e)] for e in mats[:n_dom])
+    cold_dom_achieved = sum(e["bytes"][e["fmt"]] for e in mats[:n_dom]) / (cold_dom_ms * 1e-3) / 1e9
     value = useful / (ms_per_step * 1e-3) / 1e9
     achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
     traffic = load_traffic(dom_key)
 
+    def rate(pairs):
+        tb = sum(bb for bb, _ in pairs)
+        tt = sum(tm for _, tm in pairs) * 1e-3
+        return round(tb / tt / 1e9, 1), round(tb / tt / 1e9 / HBM_PEAK_GBPS, 4)
+
     per_format = {}
-    for fmt in range(4):
+    for fmt in range(NF):
         ok = [e for e in mats if np.isfinite(e["times"][fmt])]
         if not ok:
             continue
-        tb = sum(e["bytes"][fmt] for e in ok)
-        tt = sum(e["times"][fmt] for e in ok) * 1e-3
+        g, f = rate([(e["bytes"][fmt], e["times"][fmt]) for e in ok])
+        d = {"matrices": len(ok), "gbps": g, "frac_of_peak": f}
         large = [e for e in ok if e["bytes"][fmt] >= 256e6]
-        d = {"matrices": len(ok), "gbps": round(tb / tt / 1e9, 1),
-             "frac_of_peak": round(tb / tt / 1e9 / HBM_PEAK_GBPS, 4)}
         if large:
-            lb = sum(e["bytes"][fmt] for e in large)
-            lt = sum(e["times"][fmt] for e in large) * 1e-3
             d["large_matrices"] = len(large)
-            d["large_gbps"] = round(lb / lt / 1e9, 1)
+            d["large_gbps"], d["large_frac"] = rate([(e["bytes"][fmt], e["times"][fmt]) for e in large])
         per_format[FMT_NAMES[fmt]] = d
-    chosen = {FMT_NAMES[f]: sum(1 for e in mats if e["fmt"] == f) for f in range(4)}
+    if all("coo_tiled_ms" in e for e in mats):
+        g, f = rate([(e["coo_tiled_bytes"], e["coo_tiled_ms"]) for e in mats])
+        d = {"matrices": len(mats), "gbps": g, "frac_of_peak": f,
+             "kernel": "tiled segmented COO (row, col, val triplets), best of its variants"}
+        large = [e for e in mats if e["coo_tiled_bytes"] >= 256e6]
+        if large:
+            d["large_matrices"] = len(large)
+            d["large_gbps"], d["large_frac"] = rate([(e["coo_tiled_bytes"], e["coo_tiled_ms"]) for e in large])
+        per_format["COO_tiled"] = d
+    # each format's useful (CSR-byte) rate per structure family, tuned cold medians
+    by_family = {}
+    for fam in sorted({e["family"] for e in mats}):
+        fm = [e for e in mats if e["family"] == fam]
+        row = {}
+        for fmt in range(NF):
+            ok = [e for e in fm if np.isfinite(e["times"][fmt])]
+            if len(ok) == len(fm):
+                row[FMT_NAMES[fmt]] = rate([(e["useful_bytes"], e["times"][fmt]) for e in ok])[0]
+        by_family[fam] = row
+    # the compile-time mode's result here: tuned variant against the library's default one
+    autotune = None
+    if all(e["default_ms"] for e in mats):
+        autotune = {}
+        for fmt in range(NF):
+            sp = [e["default_ms"][fmt] / e["times"][fmt] for e in mats if fmt in e["default_ms"]
+                  and np.isfinite(e["times"][fmt]) and e["times"][fmt] > 0]
+            if sp:
+                autotune[FMT_NAMES[fmt]] = {
+                    "matrices": len(sp), "mean_speedup": round(float(np.mean(sp)), 3),
+                    "max_speedup": round(float(np.max(sp)), 3),
+                    "sum_default_over_tuned": round(
+                        sum(e["default_ms"][fmt] for e in mats if fmt in e["default_ms"]
+                            and np.isfinite(e["times"][fmt]))
+                        / sum(e["times"][fmt] for e in mats if fmt in e["default_ms"]
+                              and np.isfinite(e["times"][fmt])), 3)}
+        autotune["note"] = ("cold medians of each format's default variant (chosen from the row "
+                            "lengths) over its tuned variant (fastest of all compiled variants)")
+    chosen = {FMT_NAMES[f]: sum(1 for e in mats if e["fmt"] == f) for f in range(NF)}
 
     cpu = None
     if not args.no_cpu:
-        threads = max(1, min(16, os.cpu_count() or 1))
-        cpu = cpu_baseline(mats, args.cpu_budget, threads)
+        # the cores this process may use (its affinity, and the OpenMP share when one is set)
+        threads = len(os.sched_getaffinity(0))
+        if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+            threads = min(threads, int(os.environ["OMP_NUM_THREADS"]))
+        cpu = cpu_baseline(mats, args.cpu_budget, max(1, threads))
 
     total_nnz = sum(e["nnz"] for e in mats)
     out = {
@@ -713,12 +806,15 @@ def main():
             "workload": f"{len(mats)} seeded single-SpMV matrices (banded, uniform random, "
                         "8x8 block diagonal, 3-D 7-point stencil; 1e5-2e6 rows, 1e6-5e7 nnz), "
                         "FP32 values, int32 indices, one y=A*x per matrix per step in the "
-                        "format and variant chosen by exhaustive autotuned timing",
+                        "format (CSR, COO, ELL, HYB, SELL, BELL) and variant chosen by "
+                        "exhaustive autotuned timing",
             "matrices": len(mats),
             "total_nnz": int(total_nnz),
             "useful_bytes_per_step": int(useful),
         },
         "value_frac_of_peak": round(value / HBM_PEAK_GBPS, 4),
+        "value_cold_scrubbed": cold_plan["useful_gbps_median"],
+        "value_cold_frac_of_peak": cold_plan["frac_of_peak_median"],
         "gflops": round(2 * total_nnz / (ms_per_step * 1e-3) / 1e9, 1),
         "kernel_ms_per_step": round(kernel_ms_per_step, 4),
         "roofline": {
@@ -736,10 +832,16 @@ def main():
             "avg_launch_us": round(dom["ms"] * 1e3 / dom["launches"], 3),
             "bytes_per_launch": round(dom["bytes"] / dom["launches"], 1),
             "instances": instances,
+            "cold_achieved": round(cold_dom_achieved, 1),
+            "cold_frac": round(cold_dom_achieved / HBM_PEAK_GBPS, 4),
+            "bytes": "as stored: the layout the chosen variant streams (padding, reordered "
+                     "copies, 16-bit rows and pointer arrays included), x once, y once",
         },
         "cpu_baseline": cpu,
         "copy_calibration_mib": args.copy_calibration,
         "per_format_tuned_cold": per_format,
+        "by_family_useful_gbps": by_family,
+        "autotune_vs_default": autotune,
         "cold_plan": cold_plan,
         "selected_formats": chosen,
         "setup_s": round(setup_s, 1),
@@ -749,9 +851,9 @@ def main():
         "power_law": power_law,
         "fp64": fp64,
         "plan": [{"name": e["name"], "fmt": e["fmt"],
-                  "variants": [e["variant"][f] for f in range(4)],
+                  "variants": [e["variant"][f] for f in range(NF)],
                   "times": [e["times"][f] if np.isfinite(e["times"][f]) else None
-                            for f in range(4)]} for e in mats],
+                            for f in range(NF)]} for e in mats],
     }
     print(json.dumps(out), flush=True)
 

@@ -253,6 +253,15 @@ spmv_status spmv_time(spmv_handle h, spmv_format f, int32_t variant, const void 
 spmv_status spmv_tune(spmv_handle h, spmv_format f, const void *x, void *y, int32_t reps,
                       int flush, int32_t *best_idx, float *best_ms, void *stream);
 
+/* Bytes of the device arrays one run of format f with `variant` (-1 = the
+ * current one) reads besides x and y: the layout that variant streams (the
+ * format arrays, or the reordered copy it uses, with their padding) and its
+ * pointer and order arrays. A run's algorithmic bytes are this plus n_cols
+ * values of x and n_rows of y (twice when beta != 0).
+ *   bytes: host pointer. Errors: INVALID_ARG, NOT_CONVERTED (the format, or
+ *   the copy the variant reads, is not built). Touches no device memory. */
+spmv_status spmv_stored_bytes(spmv_handle h, spmv_format f, int32_t variant, int64_t *bytes);
+
 /* ---- features and selection ---------------------------------------------- */
 
 /* The 12 sparsity features of the matrix, computed on the device (paper,

@@ -309,6 +309,19 @@ extern "C" spmv_status spmv_get_variant(spmv_handle h, spmv_format f, int32_t *i
     });
 }
 
+extern "C" spmv_status spmv_stored_bytes(spmv_handle h, spmv_format f, int32_t variant,
+                                         int64_t *bytes) {
+    return guard([&] {
+        check_runnable(h, f);
+        if (!bytes) fail(SPMV_ERR_INVALID_ARG, "NULL bytes");
+        const int32_t v = variant < 0 ? h->variant[f] : variant;
+        if (v >= variant_count(f, h->dt)) fail(SPMV_ERR_INVALID_ARG, "variant %d out of range", v);
+        const int64_t b = stored_bytes(h, f, v);
+        if (b < 0) fail(SPMV_ERR_NOT_CONVERTED, "the layout of variant %d is not built", v);
+        *bytes = b;
+    });
+}
+
 extern "C" spmv_status spmv_features(spmv_handle h, float *out12, void *stream) {
     return guard([&] {
         if (!h || !out12) fail(SPMV_ERR_INVALID_ARG, "NULL argument");

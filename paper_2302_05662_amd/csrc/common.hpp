@@ -292,6 +292,7 @@ int32_t default_variant(const spmv_matrix_s *h, spmv_format f);
 // False when variant idx cannot run on the layout f holds now (BELL: more rows
 // per thread than the block has).
 bool variant_applicable(const spmv_matrix_s *h, spmv_format f, int32_t idx);
+int64_t stored_bytes(const spmv_matrix_s *h, spmv_format f, int32_t idx);  // -1: not built
 bool variant_needs_panel(spmv_format f, int32_t idx);
 bool variant_needs_sorted(spmv_format f, int32_t idx);
 bool variant_needs_hyb_sorted(spmv_format f, int32_t idx);

@@ -1366,6 +1366,61 @@ int32_t default_variant(const spmv_matrix_s *h, spmv_format f) {
     return 0;
 }
 
+// Bytes of the device arrays one run of (f, idx) reads besides x and y: the
+// layout the variant streams, with its padding and its pointer and order arrays.
+// -1 when that layout is not built.
+int64_t stored_bytes(const spmv_matrix_s *h, spmv_format f, int32_t idx) {
+    const auto &t = table(f);
+    if (idx < 0 || idx >= (int32_t)t.size()) return -1;
+    const spmv_variant_info &info = t[idx].info;
+    const int64_t v = (int64_t)dtype_size(h->dt), n = h->n_rows, nnz = h->nnz;
+    auto sorted_bytes = [&](const SortedPart &P) -> int64_t {
+        if (!P.built) return -1;
+        return P.stream * (4 + v + (P.row16 ? 2 : 0)) + 3 * (int64_t)(P.blocks + 1) * 4;
+    };
+    switch (info.kernel) {
+        case SPMV_KERNEL_CSR_SCALAR:
+        case SPMV_KERNEL_CSR_VECTOR: return (n + 1) * 4 + nnz * (4 + v);
+        case SPMV_KERNEL_CSR_STREAM:
+            if (!h->csr_blocks.built) return -1;
+            return (n + 1) * 4 + nnz * (4 + v) + (int64_t)(h->csr_blocks.blocks + 1) * 4;
+        case SPMV_KERNEL_COO: return nnz * (8 + v);
+        case SPMV_KERNEL_COO_PANEL:
+            if (!h->panel.built) return -1;
+            return h->panel.stream * (4 + v) +
+                   (ceil_div(n, std::max(h->panel.rows_per_wave, 1)) + 1) * 4;
+        case SPMV_KERNEL_COO_SORTED: return sorted_bytes(h->sorted);
+        case SPMV_KERNEL_COO_SPLIT: {
+            if (!h->split.built) return -1;
+            int64_t e = 0;
+            for (int64_t c : h->split.count) e += c;
+            return e * (8 + v);
+        }
+        case SPMV_KERNEL_ELL:
+            if (!h->ell.built) return -1;
+            return (int64_t)h->ell.K * h->ell.pitch * (4 + v);
+        case SPMV_KERNEL_HYB: {
+            if (!h->hyb.built) return -1;
+            const int64_t ell = (int64_t)h->hyb.K * h->hyb.pitch * (4 + v);
+            if (info.pipelined == 1) {
+                const int64_t tb = h->hyb.nnz_tail > 0 ? sorted_bytes(h->hyb_sorted) : 0;
+                return tb < 0 ? -1 : ell + tb;
+            }
+            return ell + h->hyb.nnz_tail * (8 + v);
+        }
+        case SPMV_KERNEL_SELL:
+            if (!h->sell.built) return -1;
+            return h->sell.slots * (4 + v) + (int64_t)(h->sell.n_slices + 1) * 8 +
+                   (h->sell.sigma > 1 ? 4 * n : 0);
+        case SPMV_KERNEL_BELL: {
+            if (!h->bell.built) return -1;
+            const int64_t slots = (int64_t)h->bell.K * h->bell.pitch;
+            return slots * 4 + slots * h->bell.b * h->bell.b * v;
+        }
+    }
+    return -1;
+}
+
 bool variant_applicable(const spmv_matrix_s *h, spmv_format f, int32_t idx) {
     const auto &t = table(f);
     if (idx < 0 || idx >= (int32_t)t.size()) return false;

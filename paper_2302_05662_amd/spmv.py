@@ -93,6 +93,7 @@ _sig("spmv_get_variant", _I32, _P, _I32, ctypes.POINTER(_I32))
 _sig("spmv_time", _I32, _P, _I32, _I32, _P, _P, _I32, _I32, ctypes.c_int, _P, _P)
 _sig("spmv_tune", _I32, _P, _I32, _P, _P, _I32, ctypes.c_int, ctypes.POINTER(_I32),
      ctypes.POINTER(_F), _P)
+_sig("spmv_stored_bytes", _I32, _P, _I32, _I32, ctypes.POINTER(_I64))
 _sig("spmv_features", _I32, _P, _P, _P)
 _sig("spmv_select_format", _I32, _P, _I32, ctypes.POINTER(_I32), _P, _P)
 
@@ -328,6 +329,14 @@ def spmv_tune(h: Handle, fmt: int, x, y, reps=10, flush=True, stream=None):
     _check(_lib.spmv_tune(h.ptr, int(fmt), px, py, int(reps), int(bool(flush)), ctypes.byref(bi),
                           ctypes.byref(bm), _stream_ptr(stream)), "spmv_tune")
     return int(bi.value), float(bm.value)
+
+
+def spmv_stored_bytes(h: Handle, fmt: int, variant: int = -1) -> int:
+    """Bytes a run of (fmt, variant) reads besides x and y (its layout, padding included)."""
+    out = _I64()
+    _check(_lib.spmv_stored_bytes(h.ptr, int(fmt), int(variant), ctypes.byref(out)),
+           "spmv_stored_bytes")
+    return int(out.value)
 
 
 def spmv_features(h: Handle, stream=None) -> np.ndarray:
