@@ -289,6 +289,49 @@ spmv_status spmv_features(spmv_handle h, float *out12, void *stream);
 spmv_status spmv_select_format(spmv_handle h, spmv_select_mode m, spmv_format *out,
                                float *out_scores, void *stream);
 
+/* ---- overhead-aware run-time mode (paper, Method: run-time optimisation mode,
+ * step 3: the overhead of the switch is estimated and the matrix is converted
+ * only when the gain pays for it; Results: run-time prediction overhead, the
+ * regressors for the feature-extraction and conversion latencies) ----------
+ *
+ * A run-time model is SPMV_RUNTIME_MODEL floats: for each format f (0..5), 13
+ * weights w[f] of a linear model of log(median SpMV time in ms) over the
+ * selector's 12 inputs (log2(1 + v) on features 0-6, 8, 9; raw 7, 10, 11) plus
+ * an intercept (w[f][12]); then, for each format, the conversion latency in ms
+ * as c0 + c1 * (nnz / 1e6) + c2 * (n_rows / 1e6) (CSR and COO: no conversion). */
+#define SPMV_RUNTIME_MODEL 96
+
+typedef struct spmv_runtime_decision {
+    int32_t current;       /* the format the caller runs now                          */
+    int32_t predicted;     /* the selector network's choice                           */
+    int32_t chosen;        /* predicted if converting pays, else current              */
+    int32_t converted;     /* 1 when this call converted `chosen`                     */
+    float features_ms;     /* measured: the features call                             */
+    float predict_ms;      /* measured: the network's prediction                      */
+    float convert_ms;      /* estimated conversion latency of `predicted` (0 if built) */
+    float t_current_ms;    /* estimated time of one SpMV in the current format        */
+    float t_predicted_ms;  /* estimated time of one SpMV in the predicted format      */
+    double gain_ms;        /* (t_current - t_predicted) * iterations                  */
+    double overhead_ms;    /* features + prediction + conversion                      */
+} spmv_runtime_decision;
+
+/* Install / forget the run-time model on the current device (host float[96];
+ * NULL, 0 forgets it). Errors: INVALID_ARG (size, or a non-finite value). */
+spmv_status spmv_runtime_set_model(const float *params, int64_t n);
+
+/* Run-time mode for a matrix that will take `iterations` SpMVs: compute its
+ * features (timed), ask the installed selector network for a format (timed),
+ * estimate the per-SpMV times of the current and predicted formats and the
+ * predicted format's conversion latency with the run-time model, and convert
+ * only if (t_current - t_predicted) * iterations > features + prediction +
+ * conversion. A predicted format whose conversion is refused gives way to the
+ * network's next choice. `current` must be built (CSR and COO always are).
+ *   out: host pointer. Errors: INVALID_ARG, NOT_CONVERTED (current),
+ *   NO_MODEL (no selector network or no run-time model), OOM, HIP.
+ * Synchronises `stream`. */
+spmv_status spmv_select_runtime(spmv_handle h, spmv_format current, int64_t iterations,
+                                spmv_runtime_decision *out, void *stream);
+
 /* ---- batched SpMV: many CSR matrices in one persistent launch, captured in a
  * HIP graph (the stand-in for the paper's compile-time mode, Method:
  * compile-time optimisation mode, which fixes launch settings per matrix) -- */

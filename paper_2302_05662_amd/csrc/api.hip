@@ -1,9 +1,11 @@
 // C ABI entry points of the library (declared in include/spmv.h).
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
@@ -355,6 +357,137 @@ extern "C" spmv_status spmv_select_format(spmv_handle h, spmv_select_mode m, spm
         }
         *out = f;
         if (out_scores) memcpy(out_scores, scores, sizeof(scores));
+    });
+}
+
+namespace spmv {
+namespace {
+
+struct RuntimeModels {
+    std::mutex mu;
+    bool set[64] = {};
+    float p[64][SPMV_RUNTIME_MODEL];
+};
+
+RuntimeModels &runtime_models() {
+    static RuntimeModels *r = new RuntimeModels();  // lives until process exit
+    return *r;
+}
+
+int runtime_device() {
+    int d = 0;
+    SPMV_HIP(hipGetDevice(&d));
+    if (d < 0 || d >= 64) fail(SPMV_ERR_INVALID_ARG, "device id %d", d);
+    return d;
+}
+
+// Time of one SpMV in format f (ms): exp of the run-time model's linear form over
+// the selector's inputs.
+double runtime_time_ms(const float *m, int f, const float feats[12]) {
+    double z = m[f * 13 + 12];
+    for (int i = 0; i < 12; ++i) {
+        const bool lg = i <= 6 || i == 8 || i == 9;
+        const double v = lg ? std::log2(1.0 + (double)feats[i]) : (double)feats[i];
+        z += (double)m[f * 13 + i] * v;
+    }
+    return std::exp(z);
+}
+
+double runtime_convert_ms(const float *m, int f, const spmv_matrix_s *h) {
+    if (f == SPMV_FMT_CSR || f == SPMV_FMT_COO) return 0.0;
+    const float *c = m + SPMV_NUM_FORMATS * 13 + f * 3;
+    return std::max(0.0, (double)c[0] + (double)c[1] * (h->nnz / 1e6) +
+                             (double)c[2] * (h->n_rows / 1e6));
+}
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+}  // namespace
+}  // namespace spmv
+
+extern "C" spmv_status spmv_runtime_set_model(const float *params, int64_t n) {
+    return guard([&] {
+        const int d = runtime_device();
+        RuntimeModels &R = runtime_models();
+        std::lock_guard<std::mutex> lk(R.mu);
+        if (!params && n == 0) {
+            R.set[d] = false;
+            return;
+        }
+        if (!params || n != SPMV_RUNTIME_MODEL)
+            fail(SPMV_ERR_INVALID_ARG, "expected %d floats, got %lld", SPMV_RUNTIME_MODEL, (long long)n);
+        for (int i = 0; i < SPMV_RUNTIME_MODEL; ++i)
+            if (!std::isfinite(params[i])) fail(SPMV_ERR_INVALID_ARG, "parameter %d is not finite", i);
+        memcpy(R.p[d], params, sizeof(R.p[d]));
+        R.set[d] = true;
+    });
+}
+
+extern "C" spmv_status spmv_select_runtime(spmv_handle h, spmv_format current, int64_t iterations,
+                                           spmv_runtime_decision *out, void *stream) {
+    return guard([&] {
+        if (!h || !out || iterations < 0) fail(SPMV_ERR_INVALID_ARG, "bad argument");
+        check_runnable(h, current);
+        hipStream_t s = (hipStream_t)stream;
+        float m[SPMV_RUNTIME_MODEL];
+        {
+            const int d = runtime_device();
+            RuntimeModels &R = runtime_models();
+            std::lock_guard<std::mutex> lk(R.mu);
+            if (!R.set[d]) fail(SPMV_ERR_NO_MODEL, "no run-time model on device %d", d);
+            memcpy(m, R.p[d], sizeof(m));
+        }
+        spmv_runtime_decision r{};
+        r.current = current;
+        double t0 = now_ms();
+        float feats[12];
+        compute_features(h, feats, nullptr, s);
+        r.features_ms = (float)(now_ms() - t0);
+        t0 = now_ms();
+        float scores[SPMV_NUM_FORMATS];
+        int nc = 0;
+        const spmv_status st = model_logits(feats, scores, &nc, s);
+        if (st != SPMV_OK) throw Error{st};
+        r.predict_ms = (float)(now_ms() - t0);
+        bool allowed[SPMV_NUM_FORMATS];
+        for (int i = 0; i < SPMV_NUM_FORMATS; ++i) allowed[i] = i < nc;
+        allowed[SPMV_FMT_ELL] = allowed[SPMV_FMT_ELL] &&
+                                (h->nnz == 0 || (int64_t)((h->n_rows + 63) / 64 * 64) *
+                                                        h->stats.max_len <= 8 * h->nnz);
+        r.t_current_ms = (float)runtime_time_ms(m, current, feats);
+        for (;;) {
+            int best = SPMV_FMT_CSR;
+            for (int i = 0; i < SPMV_NUM_FORMATS; ++i)
+                if (allowed[i] && (!allowed[best] || scores[i] > scores[best])) best = i;
+            const spmv_format f = (spmv_format)best;
+            r.predicted = f;
+            r.t_predicted_ms = (float)runtime_time_ms(m, f, feats);
+            r.convert_ms = format_built(h, f) ? 0.f : (float)runtime_convert_ms(m, f, h);
+            r.gain_ms = ((double)r.t_current_ms - (double)r.t_predicted_ms) * (double)iterations;
+            r.overhead_ms = (double)r.features_ms + (double)r.predict_ms + (double)r.convert_ms;
+            r.chosen = current;
+            r.converted = 0;
+            if (f == current || !(r.gain_ms > r.overhead_ms)) break;  // the switch does not pay
+            if (format_built(h, f)) {
+                r.chosen = f;
+                break;
+            }
+            try {
+                convert(h, f, -1, s);
+                r.chosen = f;
+                r.converted = 1;
+                break;
+            } catch (const Error &e) {
+                if (e.status != SPMV_ERR_NOT_APPLICABLE) throw;
+                clear_error();
+                allowed[best] = false;  // CSR and COO are always built, so this ends
+            }
+        }
+        *out = r;
     });
 }
 

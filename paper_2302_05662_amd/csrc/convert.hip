@@ -331,7 +331,7 @@ void build_sell(spmv_matrix_s *h, int32_t sigma_in, hipStream_t s) {
     SellPart P;
     std::vector<int32_t> w;
     if (sigma_in == 1 || n == 0) {
-        P.sigma = 1;
+        P.sigma = sigma_in < 0 ? 1 : sigma_in;  // with no rows every order is the same
         w = widths_of(nullptr);
     } else {
         const int32_t sig = sigma_in < 0 ? kSellSigmaWide : sigma_in;

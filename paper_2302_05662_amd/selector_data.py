@@ -9,13 +9,19 @@ For each matrix (the 2-D Laplacian and the four single-SpMV families, seeds from
 * an independent check pass: ``check_reps`` more flushed runs of each format's
   chosen variant, used only to score selections (so regret is not measured on
   the timings that made the labels);
-* the rule baseline's choice.
+* the rule baseline's choice;
+* with ``--six``: all six formats (CSR, COO, ELL, HYB, SELL, BELL), plus the
+  latency of the features call and of each format's conversion (host clock
+  around the synchronous calls) and the bytes each tuned variant streams,
+  which the overhead-aware run-time mode is fitted on.
 
 Results go to an ``.npz`` file that is rewritten every ``save_every`` matrices;
 an interrupted collection resumes from it (seeds already present are skipped).
 
 Usage: python -m paper_2302_05662_amd.selector_data OUT.npz FIRST_SEED LAST_SEED [--with-powerlaw]
-(--with-powerlaw draws from the extended family set that adds the power law.)
+       [--six] [--limit-s SECONDS]
+(--with-powerlaw draws from the extended family set that adds the power law; --limit-s
+stops after that many seconds, the saved file resuming later.)
 """
 from __future__ import annotations
 
@@ -26,13 +32,14 @@ import time
 import numpy as np
 
 FIELDS = ("seed", "family", "n_rows", "nnz", "feats", "t_label", "t_check", "variant", "rule")
+FIELDS6 = FIELDS + ("t_feat", "t_convert", "bytes")
 
 
-def _load(path):
+def _load(path, fields=FIELDS):
     if not os.path.exists(path):
-        return {k: [] for k in FIELDS}
+        return {k: [] for k in fields}
     d = np.load(path, allow_pickle=False)
-    return {k: list(d[k]) for k in FIELDS}
+    return {k: list(d[k]) for k in fields}
 
 
 def _save(path, rec):
@@ -41,14 +48,17 @@ def _save(path, rec):
     os.replace(tmp, path)
 
 
-def collect(path, seeds, tune_reps=3, check_reps=5, save_every=25, log=print, families=None):
+def collect(path, seeds, tune_reps=3, check_reps=5, save_every=25, log=print, families=None,
+            six=False, limit_s=None):
     import torch
 
     import paper_2302_05662_amd as S
     import synth
 
     torch.cuda.set_device(0)
-    rec = _load(path)
+    nf = 6 if six else 4
+    fields = FIELDS6 if six else FIELDS
+    rec = _load(path, fields)
     done = set(int(s) for s in rec["seed"])
     todo = [s for s in seeds if s not in done]
     t0 = time.perf_counter()
@@ -56,35 +66,47 @@ def collect(path, seeds, tune_reps=3, check_reps=5, save_every=25, log=print, fa
     for i, spec in enumerate(synth.config5_specs(todo, families=fams)):
         m = synth.config5_matrix(spec)
         h = S.spmv_create(m.n_rows, m.n_cols, m.row, m.col, m.values(np.float32))
+        t = time.perf_counter()
         feats = S.spmv_features(h)
+        t_feat = (time.perf_counter() - t) * 1e3
         x = torch.from_numpy(m.x(np.float32)).cuda()
         y = torch.zeros(m.n_rows, dtype=torch.float32, device="cuda")
-        t_label = np.full(4, np.inf)
-        t_check = np.full(4, np.inf)
-        variant = np.full(4, -1)
-        for fmt in range(4):
+        t_label = np.full(nf, np.inf)
+        t_check = np.full(nf, np.inf)
+        t_convert = np.zeros(nf)
+        nbytes = np.zeros(nf, np.int64)
+        variant = np.full(nf, -1)
+        for fmt in range(nf):
             try:
+                t = time.perf_counter()
                 S.spmv_convert(h, fmt)
+                t_convert[fmt] = (time.perf_counter() - t) * 1e3
             except S.SpmvError as e:
                 if e.status != "NOT_APPLICABLE":
                     raise
                 continue
             variant[fmt], t_label[fmt] = S.spmv_tune(h, fmt, x, y, reps=tune_reps, flush=True)
-        for fmt in range(4):
+            nbytes[fmt] = S.spmv_stored_bytes(h, fmt)
+        for fmt in range(nf):
             if variant[fmt] >= 0:
                 t_check[fmt] = float(np.median(S.spmv_time(h, fmt, x, y, warmup=1, reps=check_reps,
                                                            flush=True)))
         rule = S.spmv_select_format(h, S.SPMV_SELECT_RULE)[0]
-        for k, v in zip(FIELDS, (spec["seed"], spec["family"], m.n_rows, m.nnz, feats, t_label,
-                                 t_check, variant, rule)):
+        vals = [spec["seed"], spec["family"], m.n_rows, m.nnz, feats, t_label, t_check, variant, rule]
+        if six:
+            vals += [t_feat, t_convert, nbytes]
+        for k, v in zip(fields, vals):
             rec[k].append(v)
         S.spmv_destroy(h)
         del m, x, y
-        if (i + 1) % save_every == 0 or i + 1 == len(todo):
+        stop = limit_s is not None and time.perf_counter() - t0 > limit_s
+        if (i + 1) % save_every == 0 or i + 1 == len(todo) or stop:
             _save(path, rec)
         log(f"[selector-data] {len(rec['seed'])} done, seed {spec['seed']} {spec['family']} "
             f"nnz={rec['nnz'][-1]} label={int(np.argmin(t_label))} "
             f"t={np.round(t_label * 1e3, 1).tolist()} us  ({time.perf_counter() - t0:.0f}s)")
+        if stop:
+            break
     return rec
 
 
@@ -92,5 +114,8 @@ if __name__ == "__main__":
     out, first, last = sys.argv[1], int(sys.argv[2]), int(sys.argv[3])
     import synth as _synth
 
-    fams = _synth.CFG5X_FAMILIES if "--with-powerlaw" in sys.argv[4:] else None
-    collect(out, list(range(first, last + 1)), log=lambda s: print(s, flush=True), families=fams)
+    opts = sys.argv[4:]
+    fams = _synth.CFG5X_FAMILIES if "--with-powerlaw" in opts else None
+    limit = float(opts[opts.index("--limit-s") + 1]) if "--limit-s" in opts else None
+    collect(out, list(range(first, last + 1)), log=lambda s: print(s, flush=True), families=fams,
+            six="--six" in opts, limit_s=limit)

@@ -11,6 +11,11 @@ majority class.
 Usage: python -m paper_2302_05662_amd.selector_fit DATA.npz [DATA2.npz ...]
 writes selector_model.npy and selector_eval.json next to this file.
 
+python -m paper_2302_05662_amd.selector_fit --six DATA6.npz trains the six-class network
+(SELL and BELL as classes 4 and 5) on a dataset collected with ``selector_data --six`` and
+fits the overhead-aware run-time model on it; it writes selector_model6.npy,
+selector_runtime.npy and selector_eval6.json.
+
 python -m paper_2302_05662_amd.selector_fit --extended DATA.npz EXT.npz evaluates, on a
 set that adds the power-law family (seeds 7000-7599), the installed network and one
 retrained on both training splits; it writes selector_eval_extended.json and
@@ -49,6 +54,77 @@ def scores(chosen, t_check):
             "max_regret": float(np.max(r)),
             "total_time_regret": float(t_check[np.arange(len(chosen)), chosen].sum() / best.sum() - 1),
             "within_5pct": float(np.mean(r <= 0.05))}
+
+
+LOG_COLS = (0, 1, 2, 3, 4, 5, 6, 8, 9)  # the selector's log2(1 + v) inputs
+NF6 = 6
+
+
+def runtime_inputs(F):
+    """The selector's input map (before standardisation) and an intercept column."""
+    T = np.array(F, dtype=np.float64, copy=True)
+    T[:, LOG_COLS] = np.log2(1.0 + T[:, LOG_COLS])
+    return np.concatenate([T, np.ones((T.shape[0], 1))], axis=1)
+
+
+def fit_runtime(d, train):
+    """Run-time model: per format a least-squares fit of log(time ms) on the selector's inputs,
+    and of the conversion latency (ms) on 1, nnz / 1e6 and n_rows / 1e6."""
+    X = runtime_inputs(d["feats"])
+    params = np.zeros(NF6 * 13 + NF6 * 3)
+    for f in range(NF6):
+        ok = train & np.isfinite(d["t_label"][:, f])
+        w, *_ = np.linalg.lstsq(X[ok], np.log(d["t_label"][ok, f]), rcond=None)
+        params[f * 13:(f + 1) * 13] = w
+    A = np.stack([np.ones(len(d["nnz"])), d["nnz"] / 1e6, d["n_rows"] / 1e6], axis=1)
+    for f in range(2, NF6):
+        ok = train & np.isfinite(d["t_label"][:, f])
+        c, *_ = np.linalg.lstsq(A[ok], d["t_convert"][ok, f], rcond=None)
+        params[NF6 * 13 + f * 3:NF6 * 13 + f * 3 + 3] = c
+    return params.astype(np.float32)
+
+
+def runtime_eval(d, held, pred, params, iterations=(1, 10, 100, 1000, 10000)):
+    """Total time of `iterations` SpMVs starting from CSR, per held-out matrix, for: never
+    converting, always converting to the network's choice, the overhead-aware decision, and the
+    best decision in hindsight (measured check-pass times and measured conversion latencies;
+    feature and prediction latencies are paid by every mode that predicts)."""
+    X = runtime_inputs(d["feats"][held])
+    tc = d["t_check"][held]
+    conv = d["t_convert"][held]
+    feat = d["t_feat"][held]
+    nnz, n = d["nnz"][held] / 1e6, d["n_rows"][held] / 1e6
+    p = pred[held]
+    W = params[:NF6 * 13].reshape(NF6, 13).astype(np.float64)
+    Cc = params[NF6 * 13:].reshape(NF6, 3).astype(np.float64)
+    t_est = np.exp(X @ W.T)
+    c_est = np.where(np.arange(NF6)[None, :] >= 2,
+                     np.maximum(0, Cc[:, 0][None, :] + Cc[:, 1][None, :] * nnz[:, None]
+                                + Cc[:, 2][None, :] * n[:, None]), 0.0)
+    idx = np.arange(len(p))
+    out = {"log_time_abs_error_median": {}, "convert_ms_abs_error_median": {}}
+    for f in range(NF6):
+        ok = np.isfinite(tc[:, f])
+        out["log_time_abs_error_median"][str(f)] = float(np.median(np.abs(np.log(t_est[ok, f]) - np.log(tc[ok, f]))))
+        if f >= 2:
+            out["convert_ms_abs_error_median"][str(f)] = float(np.median(np.abs(c_est[ok, f] - conv[ok, f])))
+    rows = []
+    for it in iterations:
+        never = tc[:, 0] * it
+        always = feat + conv[idx, p] * (p != 0) + tc[idx, p] * it
+        gain = (t_est[:, 0] - t_est[idx, p]) * it
+        switch = (p != 0) & (gain > feat + c_est[idx, p])
+        aware = feat + np.where(switch, conv[idx, p] + tc[idx, p] * it, tc[:, 0] * it)
+        allc = np.where(np.isfinite(tc), conv + tc * it, np.inf)
+        allc[:, 0] = tc[:, 0] * it
+        best = np.minimum(never, feat + allc.min(axis=1))
+        rows.append({"iterations": it,
+                     "never_convert_over_best": float(never.sum() / best.sum()),
+                     "always_convert_over_best": float(always.sum() / best.sum()),
+                     "overhead_aware_over_best": float(aware.sum() / best.sum()),
+                     "switched_fraction": float(switch.mean())})
+    out["total_time_by_iterations"] = rows
+    return out
 
 
 def fit(d, seed=5, epochs=200):
@@ -141,7 +217,51 @@ def fit_extended(d, dx, seed=5, epochs=200):
     return retrained.cpu().numpy(), ev
 
 
+def fit6(d, seed=5, epochs=200):
+    """Six-class network and run-time model on a dataset collected with --six."""
+    import torch
+
+    import paper_2302_05662_amd as S
+    import synth
+
+    train = (d["seed"] >= TRAIN_SEEDS[0]) & (d["seed"] <= TRAIN_SEEDS[1])
+    held = (d["seed"] >= HELDOUT_SEEDS[0]) & (d["seed"] <= HELDOUT_SEEDS[1])
+    F = d["feats"].astype(np.float32)
+    y = labels_of(d["t_label"])
+    n = int(train.sum())
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    model = S.spmv_selector_train(dev(F[train]), dev(y[train]),
+                                  dev(synth.glorot_params(seed, layers=(12, 64, 64, NF6))),
+                                  dev(synth.epoch_permutations(seed, n, epochs)), epochs=epochs)
+    applicable = np.isfinite(d["t_check"]).astype(np.uint8)
+    _, cls = S.spmv_selector_predict(model, dev(F), applicable=dev(applicable))
+    pred = cls.cpu().numpy()
+    tc = d["t_check"]
+    y4 = labels_of(d["t_label"][:, :4])
+    ev = {"train_matrices": n, "heldout_matrices": int(held.sum()),
+          "label_histogram_train": np.bincount(y[train], minlength=NF6).tolist(),
+          "label_histogram_heldout": np.bincount(y[held], minlength=NF6).tolist(),
+          "train_accuracy": float(np.mean(pred[train] == y[train])),
+          "heldout_accuracy": float(np.mean(pred[held] == y[held])),
+          "model": scores(pred[held], tc[held]),
+          "always_csr": scores(np.zeros(int(held.sum()), np.int64), tc[held]),
+          "rule": scores(d["rule"][held].astype(np.int64), tc[held]),
+          "best_of_csr_coo_ell_hyb": scores(y4[held], tc[held]),
+          "label_pass_on_check_timings": scores(y[held], tc[held])}
+    rt = fit_runtime(d, train)
+    ev["runtime_mode"] = runtime_eval(d, held, pred, rt)
+    return model.cpu().numpy(), rt, ev
+
+
 if __name__ == "__main__":
+    if sys.argv[1] == "--six":
+        model, rt, ev = fit6(load([sys.argv[2]]))
+        np.save(os.path.join(HERE, "selector_model6.npy"), model)
+        np.save(os.path.join(HERE, "selector_runtime.npy"), rt)
+        with open(os.path.join(HERE, "selector_eval6.json"), "w") as fh:
+            json.dump(ev, fh, indent=1)
+        print(json.dumps(ev, indent=1))
+        sys.exit(0)
     if sys.argv[1] == "--extended":
         model, ev = fit_extended(load([sys.argv[2]]), load([sys.argv[3]]))
         np.save(os.path.join(HERE, "selector_model_extended.npy"), model)

@@ -449,6 +449,40 @@ def spmv_selector_get_weights() -> np.ndarray:
     return out
 
 
+SPMV_RUNTIME_MODEL = 96
+
+
+class spmv_runtime_decision(ctypes.Structure):
+    _fields_ = [("current", ctypes.c_int32), ("predicted", ctypes.c_int32),
+                ("chosen", ctypes.c_int32), ("converted", ctypes.c_int32),
+                ("features_ms", ctypes.c_float), ("predict_ms", ctypes.c_float),
+                ("convert_ms", ctypes.c_float), ("t_current_ms", ctypes.c_float),
+                ("t_predicted_ms", ctypes.c_float), ("gain_ms", ctypes.c_double),
+                ("overhead_ms", ctypes.c_double)]
+
+
+_sig("spmv_runtime_set_model", _I32, _P, _I64)
+_sig("spmv_select_runtime", _I32, _P, _I32, _I64, ctypes.POINTER(spmv_runtime_decision), _P)
+
+
+def spmv_runtime_set_model(params):
+    """Install the 96-float run-time model on the current device; None forgets it."""
+    if params is None:
+        _check(_lib.spmv_runtime_set_model(ctypes.c_void_p(0), 0), "spmv_runtime_set_model")
+        return
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    _check(_lib.spmv_runtime_set_model(ctypes.c_void_p(a.ctypes.data), a.size),
+           "spmv_runtime_set_model")
+
+
+def spmv_select_runtime(h: Handle, current: int, iterations: int, stream=None) -> dict:
+    """Overhead-aware run-time mode: the decision as a dict (fields of spmv_runtime_decision)."""
+    d = spmv_runtime_decision()
+    _check(_lib.spmv_select_runtime(h.ptr, int(current), int(iterations), ctypes.byref(d),
+                                    _stream_ptr(stream)), "spmv_select_runtime")
+    return {f: getattr(d, f) for f, _ in d._fields_}
+
+
 class spmv_batch_config(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("unroll", ctypes.c_int32),
                 ("passes_per_tile", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),

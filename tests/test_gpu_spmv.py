@@ -104,7 +104,7 @@ def test_sell_and_bell_layouts_every_variant(name, dtype):
     tol = C.TOL[dtype]
     layouts = [(S.SPMV_FMT_SELL, p, OF.to_sell) for p in (1, 128, 16384)] + \
               [(S.SPMV_FMT_BELL, p, OF.to_bell) for p in (2, 4, 8)]
-    ran = 0
+    ran = built = 0
     for fmt, param, build in layouts:
         try:
             build(ref, param)
@@ -115,6 +115,7 @@ def test_sell_and_bell_layouts_every_variant(name, dtype):
             assert got.value.status == "NOT_APPLICABLE"
             continue
         S.spmv_convert(h, fmt, param)
+        built += 1
         for var in range(S.spmv_variant_count(fmt, h.dtype_code)):
             if not _set_variant(h, fmt, var):
                 d = S.spmv_variant_describe(fmt, h.dtype_code, var)
@@ -127,7 +128,7 @@ def test_sell_and_bell_layouts_every_variant(name, dtype):
                 err = OS.max_row_error(yd.cpu().numpy(), y_ref, den)
                 assert err <= tol, (S.FORMAT_NAMES[fmt], param, var, a, b, err)
                 ran += 1
-    assert ran > 0 or m.nnz == 0 or m.n_rows == 0
+    assert ran > 0 or built == 0 or m.nnz == 0 or m.n_rows == 0
 
 
 def test_laplacian_integer_closed_form_bit_exact():
@@ -423,13 +424,13 @@ def test_hyb_sorted_tail_follows_a_new_split(dtype):
         S.spmv_set_variant(h, S.SPMV_FMT_HYB, tails[0])
     assert e.value.status == "NOT_CONVERTED"
     for k in (0, 1, 3, 8):
-        S.spmv_convert(h, S.SPMV_FMT_HYB, hyb_k=k)
+        S.spmv_convert(h, S.SPMV_FMT_HYB, k)
         for var in tails:
             S.spmv_set_variant(h, S.SPMV_FMT_HYB, var)
             yd = torch.from_numpy(y0.copy()).cuda()
             S.spmv_run(h, S.SPMV_FMT_HYB, a, xd, b, yd)
             assert OS.max_row_error(yd.cpu().numpy(), y_ref, den) <= C.TOL[dtype], (k, var)
-    S.spmv_convert(h, S.SPMV_FMT_HYB, hyb_k=2)  # the last variant stays set
+    S.spmv_convert(h, S.SPMV_FMT_HYB, 2)  # the last variant stays set
     yd = torch.from_numpy(y0.copy()).cuda()
     S.spmv_run(h, S.SPMV_FMT_HYB, a, xd, b, yd)
     assert OS.max_row_error(yd.cpu().numpy(), y_ref, den) <= C.TOL[dtype]
