@@ -275,6 +275,22 @@ spmv_status spmv_stored_bytes(spmv_handle h, spmv_format f, int32_t variant, int
  *   out12: host pointer, float[12]. Synchronises `stream`. */
 spmv_status spmv_features(spmv_handle h, float *out12, void *stream);
 
+/* Longest row spmv_features_noalloc accepts. */
+#define SPMV_FEATURES_NOALLOC_MAX_LEN 262143
+
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): spmv_features with every temporary
+ * (row-length histogram and its prefix sums, scan tile sums, statistics,
+ * result words) in one file-scope device array of about 2 MiB per device,
+ * held until the process ends. Calls no hipMalloc or hipFree; clears what it
+ * uses with a fill kernel before each run. All calls on one device share that
+ * array, so calls that overlap in time on one device (other threads or
+ * streams) race; serialise them.
+ *   out12: host pointer, float[12]; same values as spmv_features.
+ * Errors: INVALID_ARG (NULL argument, or a row longer than
+ * SPMV_FEATURES_NOALLOC_MAX_LEN), HIP. Synchronises `stream`. */
+spmv_status spmv_features_noalloc(spmv_handle h, float *out12, void *stream);
+
 /* Choose the format for this matrix (paper, Method: run-time optimisation
  * mode, steps 1-2; Predicting optimal configuration parameters).
  *   MODEL: features -> selector network -> argmax over applicable formats

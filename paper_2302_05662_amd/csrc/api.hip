@@ -331,6 +331,13 @@ extern "C" spmv_status spmv_features(spmv_handle h, float *out12, void *stream) 
     });
 }
 
+extern "C" spmv_status spmv_features_noalloc(spmv_handle h, float *out12, void *stream) {
+    return guard([&] {
+        if (!h || !out12) fail(SPMV_ERR_INVALID_ARG, "NULL argument");
+        compute_features_noalloc(h, out12, (hipStream_t)stream);
+    });
+}
+
 extern "C" spmv_status spmv_select_format(spmv_handle h, spmv_select_mode m, spmv_format *out,
                                           float *out_scores, void *stream) {
     return guard([&] {

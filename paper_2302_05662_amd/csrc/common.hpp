@@ -237,6 +237,10 @@ namespace spmv {
 
 // ingest.hip
 void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s);
+// The same scan with caller-provided tile sums (at most min(sums_cap, 2048) of
+// them, so n <= 2048 * 2048); allocates nothing and does not synchronise.
+void exclusive_scan_i32_ws(const int32_t *in, int32_t *out, int64_t n, int32_t *sums,
+                           int64_t sums_cap, hipStream_t s);
 // Stable LSD radix sort of n 64-bit keys (the low `bits` bits) carrying a
 // 32-bit payload; on return `keys` and `payload` hold the sorted pairs.
 void radix_sort_pairs(DevBuf &keys, DevBuf &payload, int64_t n, int bits, hipStream_t s);
@@ -310,6 +314,9 @@ int64_t coo_partials_bytes(int64_t nnz, spmv_dtype dt);
 
 // features.hip
 void compute_features(spmv_matrix_s *h, float out[12], int32_t *hyb_width, hipStream_t s);
+// The same features with every temporary in a file-scope device array (no
+// allocation); rows longer than SPMV_FEATURES_NOALLOC_MAX_LEN are refused.
+void compute_features_noalloc(spmv_matrix_s *h, float out[12], hipStream_t s);
 
 // timing.hip
 void flush_caches(hipStream_t s);

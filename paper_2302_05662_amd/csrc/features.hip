@@ -9,6 +9,7 @@
 // Integer statistics are exact; the moments are formed in FP64 from the
 // exact integer sums.
 #include <algorithm>
+#include <mutex>
 
 #include "common.hpp"
 
@@ -143,44 +144,112 @@ struct FeatureRun {
     int32_t hyb_width;
 };
 
-FeatureRun run_features(spmv_matrix_s *h, hipStream_t s) {
+// Device memory one feature run works in: the histogram and its prefix sums
+// (n_bins each), the scan's tile sums, the statistics and the 13-word result.
+struct FeatureWork {
+    int32_t *hist, *cum, *sums;
+    int64_t sums_cap;
+    Stats *st;
+    float *out;  // 12 features, then the HYB width as an int32
+};
+
+__global__ __launch_bounds__(kBlock) void zero_words(int64_t n, uint32_t *__restrict__ p) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        p[i] = 0u;
+}
+
+// Clears the histogram and the statistics with a fill kernel (no memset node
+// lands in a caller's graph), then runs the feature kernels and copies the
+// result to the host (synchronises). `ws` selects the scan with caller-given
+// tile sums; otherwise the scan allocates its own.
+FeatureRun run_features_in(spmv_matrix_s *h, const FeatureWork &w, bool ws, hipStream_t s) {
     const int32_t n = h->n_rows;
+    const int32_t n_bins = h->stats.max_len + 1;
+    zero_words<<<(int)std::min<int64_t>(ceil_div(n_bins, kBlock), 1024), kBlock, 0, s>>>(
+        n_bins, (uint32_t *)w.hist);
+    SPMV_CHECK_LAUNCH();
+    static_assert(sizeof(Stats) % 4 == 0, "Stats is cleared as words");
+    zero_words<<<1, kBlock, 0, s>>>(sizeof(Stats) / 4, (uint32_t *)w.st);
+    SPMV_CHECK_LAUNCH();
+    if (n > 0) {
+        const int g = (int)std::min<int64_t>(ceil_div(n, kBlock), 1024);
+        length_histogram<<<g, kBlock, 0, s>>>(n, h->row_ptr.as<int32_t>(), n_bins, w.hist, w.st);
+        SPMV_CHECK_LAUNCH();
+        if (ws) exclusive_scan_i32_ws(w.hist, w.cum, n_bins, w.sums, w.sums_cap, s);
+        else exclusive_scan_i32(w.hist, w.cum, n_bins, s);
+        const int gb = (int)std::min<int64_t>(ceil_div(n_bins, kBlock), 1024);
+        order_statistics<<<gb, kBlock, 0, s>>>(n_bins, w.hist, w.cum, (n - 1) / 2, n / 2,
+                                               n - hyb_rows(n), w.st);
+        SPMV_CHECK_LAUNCH();
+        tail_size<<<gb, kBlock, 0, s>>>(n_bins, w.hist, w.st);
+        SPMV_CHECK_LAUNCH();
+        if (h->nnz > 0) {
+            const int ge = (int)std::min<int64_t>(ceil_div(h->nnz, kBlock), 2048);
+            bandwidth_kernel<<<ge, kBlock, 0, s>>>(h->nnz, h->row.as<int32_t>(),
+                                                   h->col.as<int32_t>(), w.st);
+            SPMV_CHECK_LAUNCH();
+        }
+    }
+    assemble_features<<<1, 64, 0, s>>>(n, h->n_cols, h->nnz, h->stats.max_len, w.st, w.out,
+                                       (int32_t *)(w.out + 12));
+    SPMV_CHECK_LAUNCH();
+    FeatureRun r;
+    SPMV_HIP(hipMemcpyAsync(r.feats, w.out, 12 * sizeof(float), hipMemcpyDeviceToHost, s));
+    SPMV_HIP(hipMemcpyAsync(&r.hyb_width, w.out + 12, 4, hipMemcpyDeviceToHost, s));
+    SPMV_HIP(hipStreamSynchronize(s));
+    return r;
+}
+
+FeatureRun run_features(spmv_matrix_s *h, hipStream_t s) {
     const int32_t n_bins = h->stats.max_len + 1;
     DevBuf hist, cum, st, out;
     hist.alloc((int64_t)n_bins * 4);
     cum.alloc((int64_t)n_bins * 4);
     st.alloc(sizeof(Stats));
     out.alloc(12 * sizeof(float) + sizeof(int32_t));
-    SPMV_HIP(hipMemsetAsync(hist.p, 0, (int64_t)n_bins * 4, s));
-    SPMV_HIP(hipMemsetAsync(st.p, 0, sizeof(Stats), s));
-    Stats *dst = st.as<Stats>();
-    if (n > 0) {
-        const int g = (int)std::min<int64_t>(ceil_div(n, kBlock), 1024);
-        length_histogram<<<g, kBlock, 0, s>>>(n, h->row_ptr.as<int32_t>(), n_bins,
-                                              hist.as<int32_t>(), dst);
-        SPMV_CHECK_LAUNCH();
-        exclusive_scan_i32(hist.as<int32_t>(), cum.as<int32_t>(), n_bins, s);
-        const int gb = (int)std::min<int64_t>(ceil_div(n_bins, kBlock), 1024);
-        order_statistics<<<gb, kBlock, 0, s>>>(n_bins, hist.as<int32_t>(), cum.as<int32_t>(),
-                                               (n - 1) / 2, n / 2, n - hyb_rows(n), dst);
-        SPMV_CHECK_LAUNCH();
-        tail_size<<<gb, kBlock, 0, s>>>(n_bins, hist.as<int32_t>(), dst);
-        SPMV_CHECK_LAUNCH();
-        if (h->nnz > 0) {
-            const int ge = (int)std::min<int64_t>(ceil_div(h->nnz, kBlock), 2048);
-            bandwidth_kernel<<<ge, kBlock, 0, s>>>(h->nnz, h->row.as<int32_t>(),
-                                                   h->col.as<int32_t>(), dst);
-            SPMV_CHECK_LAUNCH();
-        }
+    const FeatureWork w{hist.as<int32_t>(), cum.as<int32_t>(), nullptr, 0, st.as<Stats>(),
+                        out.as<float>()};
+    return run_features_in(h, w, false, s);
+}
+
+// ---- the allocation-free variant -------------------------------------------------
+//
+// One file-scope device array serves every call on a device: histogram and
+// prefix sums of up to kNoAllocBins bins, the scan's tile sums, the statistics
+// and the result. Host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device.
+
+constexpr int64_t kNoAllocBins = SPMV_FEATURES_NOALLOC_MAX_LEN + 1;
+constexpr int64_t kScanTile = 2048;  // elements per scan tile (the scan's workgroup tile)
+constexpr int64_t kNoAllocSums = (kNoAllocBins + kScanTile - 1) / kScanTile;
+constexpr int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
+constexpr int64_t kOffHist = 0;
+constexpr int64_t kOffCum = kOffHist + align256(kNoAllocBins * 4);
+constexpr int64_t kOffSums = kOffCum + align256(kNoAllocBins * 4);
+constexpr int64_t kOffStats = kOffSums + align256(kNoAllocSums * 4);
+constexpr int64_t kOffOut = kOffStats + align256(sizeof(Stats));
+constexpr int64_t kScratchBytes = kOffOut + align256(13 * 4);
+static_assert(kNoAllocSums <= kScanTile, "two-level scan");
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+unsigned char *scratch_on_current_device() {
+    int dev = 0;
+    SPMV_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) fail(SPMV_ERR_INVALID_ARG, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        SPMV_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) fail(SPMV_ERR_HIP, "no device address for the feature scratch array");
+        g_scratch_ptr[dev] = p;
     }
-    assemble_features<<<1, 64, 0, s>>>(n, h->n_cols, h->nnz, h->stats.max_len, dst,
-                                       out.as<float>(), (int32_t *)(out.as<float>() + 12));
-    SPMV_CHECK_LAUNCH();
-    FeatureRun r;
-    SPMV_HIP(hipMemcpyAsync(r.feats, out.p, 12 * sizeof(float), hipMemcpyDeviceToHost, s));
-    SPMV_HIP(hipMemcpyAsync(&r.hyb_width, out.as<float>() + 12, 4, hipMemcpyDeviceToHost, s));
-    SPMV_HIP(hipStreamSynchronize(s));
-    return r;
+    return (unsigned char *)g_scratch_ptr[dev];
 }
 
 }  // namespace
@@ -192,5 +261,18 @@ void compute_features(spmv_matrix_s *h, float out[12], int32_t *hyb_width, hipSt
 }
 
 int32_t hyb_rule_width(spmv_matrix_s *h, hipStream_t s) { return run_features(h, s).hyb_width; }
+
+void compute_features_noalloc(spmv_matrix_s *h, float out[12], hipStream_t s) {
+    if ((int64_t)h->stats.max_len + 1 > kNoAllocBins)
+        fail(SPMV_ERR_INVALID_ARG,
+             "longest row has %d entries; the allocation-free feature call takes at most %d",
+             h->stats.max_len, SPMV_FEATURES_NOALLOC_MAX_LEN);
+    unsigned char *base = scratch_on_current_device();
+    const FeatureWork w{(int32_t *)(base + kOffHist), (int32_t *)(base + kOffCum),
+                        (int32_t *)(base + kOffSums), kNoAllocSums, (Stats *)(base + kOffStats),
+                        (float *)(base + kOffOut)};
+    const FeatureRun r = run_features_in(h, w, true, s);
+    for (int i = 0; i < 12; ++i) out[i] = r.feats[i];
+}
 
 }  // namespace spmv

@@ -317,6 +317,26 @@ void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t 
     SPMV_HIP(hipStreamSynchronize(s));  // `sums` is freed on return
 }
 
+void exclusive_scan_i32_ws(const int32_t *in, int32_t *out, int64_t n, int32_t *sums,
+                           int64_t sums_cap, hipStream_t s) {
+    if (n <= 0) return;
+    const int64_t tiles = ceil_div(n, kTile);
+    if (tiles == 1) {
+        scan_tiles<<<1, kBlock, 0, s>>>(in, n, out, nullptr);
+        SPMV_CHECK_LAUNCH();
+        return;
+    }
+    if (tiles > kTile || tiles > sums_cap)
+        fail(SPMV_ERR_INVALID_ARG, "scan of %lld elements needs %lld tile sums, workspace holds %lld",
+             (long long)n, (long long)tiles, (long long)std::min<int64_t>(sums_cap, kTile));
+    scan_tile_sums<<<(int)tiles, kBlock, 0, s>>>(in, n, sums);
+    SPMV_CHECK_LAUNCH();
+    scan_tiles<<<1, kBlock, 0, s>>>(sums, tiles, sums, nullptr);  // one tile: in place
+    SPMV_CHECK_LAUNCH();
+    scan_tiles<<<(int)tiles, kBlock, 0, s>>>(in, n, out, sums);
+    SPMV_CHECK_LAUNCH();
+}
+
 int32_t device_max_row_len(const int32_t *row_ptr, int32_t n_rows, hipStream_t s) {
     if (n_rows <= 0) return 0;
     DevBuf out;

@@ -95,6 +95,7 @@ _sig("spmv_tune", _I32, _P, _I32, _P, _P, _I32, ctypes.c_int, ctypes.POINTER(_I3
      ctypes.POINTER(_F), _P)
 _sig("spmv_stored_bytes", _I32, _P, _I32, _I32, ctypes.POINTER(_I64))
 _sig("spmv_features", _I32, _P, _P, _P)
+_sig("spmv_features_noalloc", _I32, _P, _P, _P)
 _sig("spmv_select_format", _I32, _P, _I32, ctypes.POINTER(_I32), _P, _P)
 
 
@@ -343,6 +344,17 @@ def spmv_features(h: Handle, stream=None) -> np.ndarray:
     out = np.zeros(12, dtype=np.float32)
     _check(_lib.spmv_features(h.ptr, ctypes.c_void_p(out.ctypes.data), _stream_ptr(stream)),
            "spmv_features")
+    return out
+
+
+SPMV_FEATURES_NOALLOC_MAX_LEN = 262143  # longest row spmv_features_noalloc accepts
+
+
+def spmv_features_noalloc(h: Handle, stream=None) -> np.ndarray:
+    """spmv_features with its temporaries in the library's fixed device array."""
+    out = np.zeros(12, dtype=np.float32)
+    _check(_lib.spmv_features_noalloc(h.ptr, ctypes.c_void_p(out.ctypes.data),
+                                      _stream_ptr(stream)), "spmv_features_noalloc")
     return out
 
 

@@ -3,6 +3,8 @@
 Only host-side entry points that touch no GPU are called here.
 """
 import ctypes
+import os
+import re
 
 import pytest
 
@@ -41,3 +43,12 @@ def test_status_strings():
     assert S.spmv_status_string(0) == "ok"
     assert S.spmv_status_string(5) == "format not applicable"
     assert S.spmv_status_string(99) == "unknown status"
+
+
+def test_header_defines_match_binding():
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    text = open(os.path.join(root, "include", "spmv.h")).read()
+    defines = dict(re.findall(r"#define\s+(SPMV_[A-Z0-9_]+)\s+(\d+)", text))
+    assert defines, "no numeric defines found"
+    for name, value in defines.items():
+        assert getattr(S, name) == int(value), name
