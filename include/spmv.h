@@ -262,6 +262,39 @@ spmv_status spmv_tune(spmv_handle h, spmv_format f, const void *x, void *y, int3
  *   the copy the variant reads, is not built). Touches no device memory. */
 spmv_status spmv_stored_bytes(spmv_handle h, spmv_format f, int32_t variant, int64_t *bytes);
 
+/* ---- energy, average power and efficiency (paper, Experimental Setup: GPU
+ * performance monitoring -- energy, average power and MFLOPS per watt are
+ * measured beside latency while the kernel repeats; Results of the run-time
+ * optimisation mode -- the format moves power and efficiency) ------------- */
+
+typedef struct spmv_energy_result {
+    double seconds;         /* interval between the two counter updates (firmware clock) */
+    double joules;          /* board energy over that interval                           */
+    double watts;           /* joules / seconds: average board power under the load      */
+    int64_t runs;           /* SpMVs enqueued between the two updates                    */
+    double ms_per_run;      /* HIP-event time of those runs back to back, per run        */
+    double joules_per_run;  /* watts * ms_per_run: energy of one SpMV                    */
+    double mflops_per_watt; /* 2 nnz / joules_per_run / 1e6                              */
+} spmv_energy_result;
+
+/* Run format f (variant, -1 = the current one) back to back with alpha = 1,
+ * beta = 0 on `stream` and read the GPU's energy accumulator (amd-smi, matched
+ * to the current HIP device by PCI id): after a 0.1 s warm period, wait for a
+ * counter update, keep running for at least `seconds`, wait for the next
+ * update; both updates fall inside the busy period. y is overwritten. The
+ * board power includes the idle draw (see spmv_idle_power).
+ *   x, y: device pointers as for spmv_run. seconds in (0, 60]. out: host.
+ * Errors: INVALID_ARG, NOT_CONVERTED, NOT_APPLICABLE (no energy counter for
+ * this device, it did not advance, or the variant does not apply), HIP.
+ * Synchronises `stream`; takes about seconds + 0.2 s. */
+spmv_status spmv_energy(spmv_handle h, spmv_format f, int32_t variant, const void *x, void *y,
+                        double seconds, spmv_energy_result *out, void *stream);
+
+/* Average board power over at least `seconds` between two counter updates,
+ * with no work of this library (other work on the device counts).
+ *   watts: host. Errors: INVALID_ARG, NOT_APPLICABLE, HIP. Synchronises the device. */
+spmv_status spmv_idle_power(double seconds, double *watts);
+
 /* ---- features and selection ---------------------------------------------- */
 
 /* The 12 sparsity features of the matrix, computed on the device (paper,

@@ -20,6 +20,7 @@ an interrupted collection resumes from it (seeds already present are skipped).
 
 Usage: python -m paper_2302_05662_amd.selector_data OUT.npz FIRST_SEED LAST_SEED [--with-powerlaw]
        [--six] [--limit-s SECONDS]
+       python -m paper_2302_05662_amd.selector_data --energy OUT.npz FIRST LAST STEP [--limit-s S]
 (--with-powerlaw draws from the extended family set that adds the power law; --limit-s
 stops after that many seconds, the saved file resuming later.)
 """
@@ -110,7 +111,81 @@ def collect(path, seeds, tune_reps=3, check_reps=5, save_every=25, log=print, fa
     return rec
 
 
+FIELDS_ENERGY = ("seed", "family", "n_rows", "nnz", "feats", "variant", "t_label", "rule",
+                 "e_label", "w_label", "ms_label", "e_check", "w_check", "ms_check", "idle_w")
+
+
+def collect_energy(path, seeds, seconds=0.1, tune_reps=3, save_every=10, log=print, limit_s=None):
+    """Energy labels: per matrix, every format (of six) autotuned for time, then the
+    board energy and average power of its tuned variant run back to back
+    (``spmv_energy``), twice: a label pass and an independent check pass."""
+    import torch
+
+    import paper_2302_05662_amd as S
+    import synth
+
+    torch.cuda.set_device(0)
+    nf = 6
+    rec = _load(path, FIELDS_ENERGY)
+    done = set(int(s) for s in rec["seed"])
+    todo = [s for s in seeds if s not in done]
+    t0 = time.perf_counter()
+    for i, spec in enumerate(synth.config5_specs(todo)):
+        m = synth.config5_matrix(spec)
+        h = S.spmv_create(m.n_rows, m.n_cols, m.row, m.col, m.values(np.float32))
+        feats = S.spmv_features(h)
+        x = torch.from_numpy(m.x(np.float32)).cuda()
+        y = torch.zeros(m.n_rows, dtype=torch.float32, device="cuda")
+        variant = np.full(nf, -1)
+        t_label = np.full(nf, np.inf)
+        e = {k: np.full(nf, np.inf) for k in ("e_label", "w_label", "ms_label", "e_check",
+                                              "w_check", "ms_check")}
+        for fmt in range(nf):
+            try:
+                S.spmv_convert(h, fmt)
+            except S.SpmvError as err:
+                if err.status != "NOT_APPLICABLE":
+                    raise
+                continue
+            variant[fmt], t_label[fmt] = S.spmv_tune(h, fmt, x, y, reps=tune_reps, flush=True)
+        idle = S.spmv_idle_power(seconds)
+        for tag in ("label", "check"):
+            for fmt in range(nf):
+                if variant[fmt] < 0:
+                    continue
+                r = S.spmv_energy(h, fmt, x, y, seconds=seconds)
+                e[f"e_{tag}"][fmt] = r["joules_per_run"]
+                e[f"w_{tag}"][fmt] = r["watts"]
+                e[f"ms_{tag}"][fmt] = r["ms_per_run"]
+        rule = S.spmv_select_format(h, S.SPMV_SELECT_RULE)[0]
+        vals = [spec["seed"], spec["family"], m.n_rows, m.nnz, feats, variant, t_label, rule,
+                e["e_label"], e["w_label"], e["ms_label"], e["e_check"], e["w_check"],
+                e["ms_check"], idle]
+        for k, v in zip(FIELDS_ENERGY, vals):
+            rec[k].append(v)
+        S.spmv_destroy(h)
+        del m, x, y
+        stop = limit_s is not None and time.perf_counter() - t0 > limit_s
+        if (i + 1) % save_every == 0 or i + 1 == len(todo) or stop:
+            _save(path, rec)
+        log(f"[energy-data] {len(rec['seed'])} done, seed {spec['seed']} {spec['family']} "
+            f"nnz={rec['nnz'][-1]} uJ={np.round(e['e_label'] * 1e6, 1).tolist()} "
+            f"W={np.round(e['w_label'], 0).tolist()} idle={idle:.0f}W "
+            f"({time.perf_counter() - t0:.0f}s)")
+        if stop:
+            break
+    return rec
+
+
 if __name__ == "__main__":
+    if sys.argv[1] == "--energy":
+        # --energy OUT.npz FIRST LAST STEP [--limit-s SECONDS]
+        out, first, last, step = sys.argv[2], int(sys.argv[3]), int(sys.argv[4]), int(sys.argv[5])
+        opts = sys.argv[6:]
+        limit = float(opts[opts.index("--limit-s") + 1]) if "--limit-s" in opts else None
+        collect_energy(out, list(range(first, last + 1, step)), log=lambda s: print(s, flush=True),
+                       limit_s=limit)
+        sys.exit(0)
     out, first, last = sys.argv[1], int(sys.argv[2]), int(sys.argv[3])
     import synth as _synth
 

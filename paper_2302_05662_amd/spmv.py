@@ -91,6 +91,18 @@ _sig("spmv_variant_describe", _I32, _I32, _I32, _I32, ctypes.POINTER(spmv_varian
 _sig("spmv_set_variant", _I32, _P, _I32, _I32)
 _sig("spmv_get_variant", _I32, _P, _I32, ctypes.POINTER(_I32))
 _sig("spmv_time", _I32, _P, _I32, _I32, _P, _P, _I32, _I32, ctypes.c_int, _P, _P)
+
+
+class spmv_energy_result(ctypes.Structure):
+    _fields_ = [("seconds", ctypes.c_double), ("joules", ctypes.c_double),
+                ("watts", ctypes.c_double), ("runs", ctypes.c_int64),
+                ("ms_per_run", ctypes.c_double), ("joules_per_run", ctypes.c_double),
+                ("mflops_per_watt", ctypes.c_double)]
+
+
+_sig("spmv_energy", _I32, _P, _I32, _I32, _P, _P, ctypes.c_double,
+     ctypes.POINTER(spmv_energy_result), _P)
+_sig("spmv_idle_power", _I32, ctypes.c_double, ctypes.POINTER(ctypes.c_double))
 _sig("spmv_tune", _I32, _P, _I32, _P, _P, _I32, ctypes.c_int, ctypes.POINTER(_I32),
      ctypes.POINTER(_F), _P)
 _sig("spmv_stored_bytes", _I32, _P, _I32, _I32, ctypes.POINTER(_I64))
@@ -330,6 +342,23 @@ def spmv_tune(h: Handle, fmt: int, x, y, reps=10, flush=True, stream=None):
     _check(_lib.spmv_tune(h.ptr, int(fmt), px, py, int(reps), int(bool(flush)), ctypes.byref(bi),
                           ctypes.byref(bm), _stream_ptr(stream)), "spmv_tune")
     return int(bi.value), float(bm.value)
+
+
+def spmv_energy(h: Handle, fmt: int, x, y, seconds=0.25, variant=-1, stream=None) -> dict:
+    """Board energy and average power of fmt's SpMV run back to back (amd-smi counter)."""
+    px = _check_vector(x, h.n_cols, h, "x")
+    py = _check_vector(y, h.n_rows, h, "y")
+    r = spmv_energy_result()
+    _check(_lib.spmv_energy(h.ptr, int(fmt), int(variant), px, py, float(seconds), ctypes.byref(r),
+                            _stream_ptr(stream)), "spmv_energy")
+    return {k: getattr(r, k) for k, _ in spmv_energy_result._fields_}
+
+
+def spmv_idle_power(seconds=0.25) -> float:
+    """Average board power between two counter updates with no work of this library."""
+    w = ctypes.c_double()
+    _check(_lib.spmv_idle_power(float(seconds), ctypes.byref(w)), "spmv_idle_power")
+    return float(w.value)
 
 
 def spmv_stored_bytes(h: Handle, fmt: int, variant: int = -1) -> int:
