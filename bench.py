@@ -169,8 +169,13 @@ def counter_summary(fetch_csv, write_csv, bench_json, out_json):
     d = {"kernel_source_hash": kernel_source_hash(),
          "note": "HBM bytes per launch over the timed steps: FETCH_SIZE x fetch scale + "
                  "WRITE_SIZE x write scale (KiB x 1024)",
-         "fetch_scale": round(fs, 6), "write_scale": round(ws, 6),
-         "kernels": {rf["kernel"]: round(traffic)}}
+         "fetch_scale": round(fs, 6), "write_scale": round(ws, 6), "kernels": {}}
+    if os.path.exists(out_json):  # other kernels' figures, taken on the same sources, stay
+        with open(out_json) as fh:
+            old = json.load(fh)
+        if old.get("kernel_source_hash") == d["kernel_source_hash"]:
+            d["kernels"].update(old.get("kernels", {}))
+    d["kernels"][rf["kernel"]] = round(traffic)
     with open(out_json, "w") as fh:
         json.dump(d, fh, indent=1)
         fh.write("\n")
@@ -466,12 +471,20 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--matrices", type=int, default=30, help="first N of the 30 seeds")
+    ap.add_argument("--seeds", help="comma-separated seeds of the 30 (e.g. 2001,2009) instead of "
+                    "the first N: a per-matrix measurement for profiles")
     ap.add_argument("--tune-reps", type=int, default=5)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle CPU work")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-matrix batched section")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 pass over the same matrices")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="profile runs: only setup, the cold plan and the timed steps (no selector, "
+                         "power-law, FP64, batched or CPU sections)")
     ap.add_argument("--batched-matrices", type=int, default=256)
+    ap.add_argument("--format", choices=("CSR", "COO", "ELL", "HYB", "SELL", "BELL"),
+                    help="time this format (its tuned variant) on every matrix where it applies, "
+                         "instead of the fastest format: a per-kernel measurement for profiles")
     ap.add_argument("--plan", help="JSON of a previous run: reuse its format/variant per matrix "
                     "instead of tuning")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -483,6 +496,8 @@ def main():
                     help="HBM traffic of the roofline kernel from rocprofv3 FETCH_SIZE and "
                          "WRITE_SIZE runs of a --copy-calibration bench; writes OUT_JSON and exits")
     args = ap.parse_args()
+    if args.kernels_only:
+        args.no_batched = args.no_fp64 = args.no_cpu = True
     if args.trace_summary:
         trace_summary(*args.trace_summary)
         return
@@ -503,6 +518,11 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     seeds = list(synth.matrices.CFG2_SEEDS)[: args.matrices]
+    if args.seeds:
+        seeds = [int(t) for t in args.seeds.split(",")]
+        bad = [t for t in seeds if t not in synth.matrices.CFG2_SEEDS]
+        if bad:
+            sys.exit(f"--seeds: {bad} are not among the 30 single-SpMV seeds")
 
     plan = None
     if args.plan:
@@ -571,6 +591,8 @@ def main():
         for fmt in range(NF):
             entry["variant"].setdefault(fmt, -1)
         entry["fmt"] = int(np.argmin([entry["times"][f] for f in range(NF)]))
+        if args.format and np.isfinite(entry["times"][FMT_NAMES.index(args.format)]):
+            entry["fmt"] = FMT_NAMES.index(args.format)
         entry["fmt4"] = int(np.argmin([entry["times"][f] for f in range(NF4)]))
         entry["useful_bytes"] = format_bytes(0, m.n_rows, m.n_cols, m.nnz, 4)
         if not args.no_cpu:
@@ -592,7 +614,7 @@ def main():
     # Everything else that launches kernels runs before the timed region, so the
     # timed launches are the last SpMV dispatches of the run (a kernel trace's last
     # `launches` dispatches of the roofline kernel are exactly the timed ones).
-    selector = selector_section(S, torch, mats, step, args.steps)
+    selector = None if args.kernels_only else selector_section(S, torch, mats, step, args.steps)
     setup_rates = {
         "ingest_nnz_per_s": round(total_nnz_of(mats) / sum(e["t_ingest"] for e in mats), 0),
         "features_nnz_per_s": round(total_nnz_of(mats) / sum(e["t_feat"] for e in mats), 0),
@@ -603,8 +625,10 @@ def main():
         "note": "host wall clock around each synchronous call, COO already in HBM; the paper's "
                 "CPU figures are about 4.8e5 (features) and 4.3e5 (conversion) nnz/s",
     }
-    rates, power_law = ingest_unsorted(S, torch, synth, tune=plan is None)
-    setup_rates.update(rates)
+    power_law = None
+    if not args.kernels_only:
+        rates, power_law = ingest_unsorted(S, torch, synth, tune=plan is None)
+        setup_rates.update(rates)
     fp64 = None if (args.no_fp64 or plan is not None) else fp64_section(S, torch, synth, seeds)
     batched = None if args.no_batched else batched_section(S, torch, synth,
                                                            args.batched_matrices)
@@ -807,7 +831,9 @@ def main():
                         "8x8 block diagonal, 3-D 7-point stencil; 1e5-2e6 rows, 1e6-5e7 nnz), "
                         "FP32 values, int32 indices, one y=A*x per matrix per step in the "
                         "format (CSR, COO, ELL, HYB, SELL, BELL) and variant chosen by "
-                        "exhaustive autotuned timing",
+                        "exhaustive autotuned timing"
+                        + (f"; diagnostic run: {args.format} forced where it applies"
+                           if args.format else ""),
             "matrices": len(mats),
             "total_nnz": int(total_nnz),
             "useful_bytes_per_step": int(useful),

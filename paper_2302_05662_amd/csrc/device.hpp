@@ -100,6 +100,58 @@ __device__ __forceinline__ Pack<V, N> ld_xrun(const V *p) {
     return r;
 }
 
+// ---- x values of N entries that may be consecutive columns -------------------------
+//
+// A lane holding N entries whose columns are c, c+1, ..., c+N-1 (banded and
+// stencil rows, consecutive ELL rows at one slot) reads them with one vector
+// load (dword-aligned: the hardware accepts any 4-byte-aligned address) instead
+// of N gathers, so a wave's x instruction touches the few lines of a contiguous
+// run rather than N instructions touching the same lines with stride N. Other
+// lanes gather each valid entry (masked entries read x[0]). Both paths read the
+// same addresses, so the values are identical either way.
+
+typedef float f32x2a4 __attribute__((ext_vector_type(2), aligned(4)));
+typedef float f32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef double f64x2a8 __attribute__((ext_vector_type(2), aligned(8)));
+
+template <class V, int N>
+__device__ __forceinline__ void ld_x_unaligned(const V *p, V (&xv)[N]) {
+    if constexpr (N == 1) {
+        xv[0] = p[0];
+    } else if constexpr (sizeof(V) == 4 && N == 4) {
+        const f32x4a4 a = *(const f32x4a4 *)p;
+        xv[0] = a.x; xv[1] = a.y; xv[2] = a.z; xv[3] = a.w;
+    } else if constexpr (sizeof(V) == 4 && N == 2) {
+        const f32x2a4 a = *(const f32x2a4 *)p;
+        xv[0] = a.x; xv[1] = a.y;
+    } else {
+        static_assert(sizeof(V) == 8 && N % 2 == 0, "");
+#pragma unroll
+        for (int q = 0; q < N; q += 2) {
+            const f64x2a8 a = *(const f64x2a8 *)(p + q);
+            xv[q] = a.x; xv[q + 1] = a.y;
+        }
+    }
+}
+
+template <class V, int N>
+__device__ __forceinline__ void gather_x(const V *__restrict__ x, const int32_t (&c)[N],
+                                         const bool (&ok)[N], V (&xv)[N]) {
+    if constexpr (N == 1) {
+        xv[0] = x[ok[0] ? c[0] : 0];
+        return;
+    }
+    bool run = ok[0] && ok[N - 1];
+#pragma unroll
+    for (int q = 1; q < N; ++q) run = run && c[q] == c[0] + q;
+    if (run) {
+        ld_x_unaligned<V, N>(x + c[0], xv);
+    } else {
+#pragma unroll
+        for (int q = 0; q < N; ++q) xv[q] = x[ok[q] ? c[q] : 0];
+    }
+}
+
 // y_i = alpha * s + beta * y_i, with y not read when beta == 0.
 template <class V>
 __device__ __forceinline__ void store_y(V *y, int64_t i, double s, V alpha, V beta) {
@@ -136,11 +188,19 @@ __device__ __forceinline__ double csr_row_partial4(const int32_t *__restrict__ c
         }
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
+            bool ok[4];
+            int32_t cc[4];
+            V xv[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int32_t k = j + u * STEP + q;
-                if (k >= s && k < e) acc += (double)v[u].v[q] * (double)x[c[u].v[q]];
+                ok[q] = k >= s && k < e;
+                cc[q] = c[u].v[q];
             }
+            gather_x<V, 4>(x, cc, ok, xv);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (ok[q]) acc += (double)v[u].v[q] * (double)xv[q];
         }
     }
     return acc;
@@ -190,11 +250,13 @@ __device__ __forceinline__ void csr_rows_pipelined(const int32_t *__restrict__ c
     while (__any(active)) {
         V xv[4];
         bool ok[4];
+        int32_t cc[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             ok[q] = active && (j + q >= s) && (j + q < e);
-            xv[q] = x[ok[q] ? c.v[q] : 0];
+            cc[q] = c.v[q];
         }
+        gather_x<V, 4>(x, cc, ok, xv);
         __builtin_amdgcn_sched_barrier(0);  // gathers issue before the prefetch
         const bool row_done = active && (t + 1 >= chunks);
         const int pn = row_done ? p + 1 : p;

@@ -157,22 +157,31 @@ __global__ __launch_bounds__(BLOCK) void csr_stream_kernel(const int32_t *__rest
                 const Pack<int32_t, 4> c = ld_i32<4>(col + q);
                 const Pack<V, 4> v = ld_val<4>(val + q);
                 V xv[4];
+                bool ok[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const bool ok = q + j >= e0 && q + j < e1;
-                    xv[j] = x[ok ? c.v[j] : 0];
-                }
+                for (int j = 0; j < 4; ++j) ok[j] = q + j >= e0 && q + j < e1;
+                gather_x<V, 4>(x, c.v, ok, xv);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     s_p[q - base + j] = (double)v.v[j] * (double)xv[j];
             }
         }
         __syncthreads();
-        for (int32_t t = threadIdx.x; t < r1 - r0; t += BLOCK) {
-            const int64_t a0 = rp[r0 + t] - base, a1 = rp[r0 + t + 1] - base;
+        // LP lanes per row (a power of two, block-uniform): lane q of a row adds its
+        // products q, q + LP, ... and the LP partial sums meet in a fixed shuffle tree
+        const int32_t nr = r1 - r0;
+        int lp = 1;
+        while (lp < 16 && nr * lp * 2 <= BLOCK) lp *= 2;
+        for (int32_t t0 = 0; t0 < nr * lp; t0 += BLOCK) {
+            const int32_t t = t0 + threadIdx.x;
+            const int32_t r = t / lp, q = t % lp;
             double s = 0.0;
-            for (int64_t k = a0; k < a1; ++k) s += s_p[k];
-            store_y(y, r0 + t, s, alpha, beta);
+            if (r < nr) {
+                const int64_t a0 = rp[r0 + r] - base, a1 = rp[r0 + r + 1] - base;
+                for (int64_t k = a0 + q; k < a1; k += lp) s += s_p[k];
+            }
+            for (int off = lp / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
+            if (r < nr && q == 0) store_y(y, r0 + r, s, alpha, beta);
         }
         return;
     }
@@ -221,10 +230,8 @@ __global__ __launch_bounds__(BLOCK) void ell_pipe_kernel(int32_t n_rows, int32_t
         V xv[RPT];
         bool ok[RPT];
 #pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-            ok[q] = c.v[q] >= 0;
-            xv[q] = x[ok[q] ? c.v[q] : 0];
-        }
+        for (int q = 0; q < RPT; ++q) ok[q] = c.v[q] >= 0;
+        gather_x<V, RPT>(x, c.v, ok, xv);
         __builtin_amdgcn_sched_barrier(0);  // gathers issue before the prefetch ...
         const int64_t off = (int64_t)(ahead < K ? ahead : K - 1) * pitch + i0;
         cn = ld_i32<RPT>(ecol + off);
@@ -295,10 +302,8 @@ __global__ __launch_bounds__(64 * KS) void ell_ksplit_kernel(int32_t n_rows, int
         V xv[RPT];
         bool ok[RPT];
 #pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-            ok[q] = c.v[q] >= 0;
-            xv[q] = x[ok[q] ? c.v[q] : 0];
-        }
+        for (int q = 0; q < RPT; ++q) ok[q] = c.v[q] >= 0;
+        gather_x<V, RPT>(x, c.v, ok, xv);
         __builtin_amdgcn_sched_barrier(0);
         const int64_t off = (int64_t)(ahead < K ? ahead : w) * pitch + i0;
         cn = ld_i32<RPT>(ecol + off);
@@ -374,12 +379,11 @@ __global__ __launch_bounds__(BLOCK) void ell_kernel(int32_t n_rows, int32_t K, i
         V xv[UNROLL][RPT];
         bool ok[UNROLL][RPT];
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u)
+        for (int u = 0; u < UNROLL; ++u) {
 #pragma unroll
-            for (int q = 0; q < RPT; ++q) {
-                ok[u][q] = c[u].v[q] >= 0;
-                xv[u][q] = x[ok[u][q] ? c[u].v[q] : 0];
-            }
+            for (int q = 0; q < RPT; ++q) ok[u][q] = c[u].v[q] >= 0;
+            gather_x<V, RPT>(x, c[u].v, ok[u], xv[u]);
+        }
         __builtin_amdgcn_sched_barrier(0);  // every gather of the group before the products
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
@@ -429,10 +433,23 @@ __global__ __launch_bounds__(BLOCK) void coo_tile_kernel(
         Pack<int32_t, ITEMS> rr = ld_i32<ITEMS>(row + k0);
         Pack<int32_t, ITEMS> cc = ld_i32<ITEMS>(col + k0);
         Pack<V, ITEMS> vv = ld_val<ITEMS>(val + k0);
+        constexpr int G = ITEMS < 4 ? ITEMS : 4;  // x runs of up to 4 entries
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            r[i] = rr.v[i];
-            p[i] = (double)vv.v[i] * (double)x[cc.v[i]];
+        for (int g = 0; g < ITEMS; g += G) {
+            int32_t c4[G];
+            bool ok[G];
+            V xv[G];
+#pragma unroll
+            for (int i = 0; i < G; ++i) {
+                c4[i] = cc.v[g + i];
+                ok[i] = true;
+            }
+            gather_x<V, G>(x, c4, ok, xv);
+#pragma unroll
+            for (int i = 0; i < G; ++i) {
+                r[g + i] = rr.v[g + i];
+                p[g + i] = (double)vv.v[g + i] * (double)xv[i];
+            }
         }
         n_valid = ITEMS;
     } else {
@@ -599,12 +616,11 @@ __device__ __forceinline__ void sell_accumulate(const SellStep<V, UNROLL> &st,
     V xv[UNROLL][4];
     bool ok[UNROLL][4];
 #pragma unroll
-    for (int u = 0; u < UNROLL; ++u)
+    for (int u = 0; u < UNROLL; ++u) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            ok[u][q] = st.c[u].v[q] >= 0;
-            xv[u][q] = x[ok[u][q] ? st.c[u].v[q] : 0];
-        }
+        for (int q = 0; q < 4; ++q) ok[u][q] = st.c[u].v[q] >= 0;
+        gather_x<V, 4>(x, st.c[u].v, ok[u], xv[u]);
+    }
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u)
 #pragma unroll
@@ -639,12 +655,11 @@ __device__ __forceinline__ double sell_row_sum(const int32_t *__restrict__ col,
             V xv[UNROLL][4];
             bool ok[UNROLL][4];
 #pragma unroll
-            for (int u = 0; u < UNROLL; ++u)
+            for (int u = 0; u < UNROLL; ++u) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    ok[u][q] = A.c[u].v[q] >= 0;
-                    xv[u][q] = x[ok[u][q] ? A.c[u].v[q] : 0];
-                }
+                for (int q = 0; q < 4; ++q) ok[u][q] = A.c[u].v[q] >= 0;
+                gather_x<V, 4>(x, A.c[u].v, ok[u], xv[u]);
+            }
             __builtin_amdgcn_sched_barrier(0);
             const bool more = g + step < groups;
             sell_load<V, UNROLL>(B, col, val, base, more ? g + step : g0, gstride, groups, lane);
@@ -660,12 +675,11 @@ __device__ __forceinline__ double sell_row_sum(const int32_t *__restrict__ col,
             g += step;
             // same body with the buffers swapped
 #pragma unroll
-            for (int u = 0; u < UNROLL; ++u)
+            for (int u = 0; u < UNROLL; ++u) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    ok[u][q] = B.c[u].v[q] >= 0;
-                    xv[u][q] = x[ok[u][q] ? B.c[u].v[q] : 0];
-                }
+                for (int q = 0; q < 4; ++q) ok[u][q] = B.c[u].v[q] >= 0;
+                gather_x<V, 4>(x, B.c[u].v, ok[u], xv[u]);
+            }
             __builtin_amdgcn_sched_barrier(0);
             const bool more2 = g + step < groups;
             sell_load<V, UNROLL>(A, col, val, base, more2 ? g + step : g0, gstride, groups, lane);
@@ -851,10 +865,12 @@ template <class V>
 void launch_coo_arrays(int64_t nnz, int32_t n_rows, const int32_t *row, const int32_t *col,
                        const V *val, const Args &a, double *part, int items, bool accum);
 
-template <class V, int ITEMS, bool ACCUM>
+// BLOCK * ITEMS >= 512: the partial-sum buffer holds two slots per 512 entries.
+template <class V, int ITEMS, bool ACCUM, int BLOCK = 256>
 void coo_launch_impl(int64_t nnz, int32_t n_rows, const int32_t *row, const int32_t *col,
                      const V *val, const Args &a, double *part) {
-    constexpr int BLOCK = 256, TILE = BLOCK * ITEMS;
+    constexpr int TILE = BLOCK * ITEMS;
+    static_assert(TILE >= 512 && BLOCK % kWave == 0, "tile size");
     const V al = (V)a.alpha, be = (V)a.beta;
     if (nnz == 0) {
         if (!ACCUM && n_rows > 0) {
@@ -972,27 +988,27 @@ void ell_pipe_launch(const Args &a) {
     SPMV_CHECK_LAUNCH();
 }
 
-template <class V, int ITEMS>
+template <class V, int ITEMS, int BLOCK = 256>
 void coo_launch(const Args &a) {
     const spmv_matrix_s *h = a.h;
-    coo_launch_impl<V, ITEMS, false>(h->nnz, h->n_rows, h->row.as<int32_t>(), h->col.as<int32_t>(),
-                                     h->val.as<V>(), a, h->coo_partials.as<double>());
+    coo_launch_impl<V, ITEMS, false, BLOCK>(h->nnz, h->n_rows, h->row.as<int32_t>(),
+                                            h->col.as<int32_t>(), h->val.as<V>(), a,
+                                            h->coo_partials.as<double>());
 }
 
-template <class V, int RPT, int UNROLL>
+template <class V, int RPT, int UNROLL, int BLOCK = 256>
 void ell_arrays_launch(int32_t n_rows, int32_t K, int32_t pitch, const int32_t *ecol,
                        const V *evals, const Args &a) {
     if (n_rows == 0) return;
-    constexpr int BLOCK = 256;
     ell_kernel<V, BLOCK, RPT, UNROLL><<<grid_of(ceil_div(n_rows, RPT), BLOCK), BLOCK, 0, a.s>>>(
         n_rows, K, pitch, ecol, evals, (const V *)a.x, (V)a.alpha, (V)a.beta, (V *)a.y);
     SPMV_CHECK_LAUNCH();
 }
 
-template <class V, int RPT, int UNROLL>
+template <class V, int RPT, int UNROLL, int BLOCK = 256>
 void ell_launch(const Args &a) {
     const spmv_matrix_s *h = a.h;
-    ell_arrays_launch<V, RPT, UNROLL>(h->n_rows, h->ell.K, h->ell.pitch, h->ell.col.as<int32_t>(),
+    ell_arrays_launch<V, RPT, UNROLL, BLOCK>(h->n_rows, h->ell.K, h->ell.pitch, h->ell.col.as<int32_t>(),
                                       h->ell.val.as<V>(), a);
 }
 
@@ -1010,10 +1026,10 @@ void ell_ksplit_launch(const Args &a) {
     SPMV_CHECK_LAUNCH();
 }
 
-template <class V, int RPT, int ITEMS>
+template <class V, int RPT, int ITEMS, int BLOCK = 256>
 void hyb_launch(const Args &a) {
     const spmv_matrix_s *h = a.h;
-    ell_arrays_launch<V, RPT, 4>(h->n_rows, h->hyb.K, h->hyb.pitch, h->hyb.ell_col.as<int32_t>(),
+    ell_arrays_launch<V, RPT, 4, BLOCK>(h->n_rows, h->hyb.K, h->hyb.pitch, h->hyb.ell_col.as<int32_t>(),
                                  h->hyb.ell_val.as<V>(), a);
     if (h->hyb.nnz_tail > 0)
         coo_launch_impl<V, ITEMS, true>(h->hyb.nnz_tail, h->n_rows, h->hyb.tail_row.as<int32_t>(),
@@ -1178,6 +1194,22 @@ template <class V> void hyb_s2_8(const Args &a) { hyb_sorted_launch<V, 2, 8>(a);
 template <class V> void hyb_s2_16(const Args &a) { hyb_sorted_launch<V, 2, 16>(a); }
 template <class V> void hyb_1_8(const Args &a) { hyb_launch<V, 1, 8>(a); }
 template <class V> void hyb_2_4(const Args &a) { hyb_launch<V, 2, 4>(a); }
+template <class V> void hyb_4_4(const Args &a) { hyb_launch<V, 4, 4>(a); }
+template <class V> void hyb_4_8(const Args &a) { hyb_launch<V, 4, 8>(a); }
+template <class V> void hyb_s4_8(const Args &a) { hyb_sorted_launch<V, 4, 8>(a); }
+// the paper's thread-block-size knob on ELL, tiled COO and HYB's ELL part
+#define BLKV(name, call) \
+    template <class V> void name(const Args &a) { call(a); }
+BLKV(ell_b64_4_2, (ell_launch<V, 4, 2, 64>)) BLKV(ell_b128_4_2, (ell_launch<V, 4, 2, 128>))
+BLKV(ell_b512_4_2, (ell_launch<V, 4, 2, 512>)) BLKV(ell_b1024_4_2, (ell_launch<V, 4, 2, 1024>))
+BLKV(ell_b64_2_4, (ell_launch<V, 2, 4, 64>)) BLKV(ell_b128_2_4, (ell_launch<V, 2, 4, 128>))
+BLKV(ell_b512_2_4, (ell_launch<V, 2, 4, 512>)) BLKV(ell_b1024_2_4, (ell_launch<V, 2, 4, 1024>))
+BLKV(coo_b64_8, (coo_launch<V, 8, 64>)) BLKV(coo_b128_4, (coo_launch<V, 4, 128>))
+BLKV(coo_b512_4, (coo_launch<V, 4, 512>)) BLKV(coo_b1024_4, (coo_launch<V, 4, 1024>))
+BLKV(coo_b1024_2, (coo_launch<V, 2, 1024>))
+BLKV(hyb_b128_2_8, (hyb_launch<V, 2, 8, 128>)) BLKV(hyb_b512_2_8, (hyb_launch<V, 2, 8, 512>))
+BLKV(hyb_b1024_2_8, (hyb_launch<V, 2, 8, 1024>)) BLKV(hyb_b64_1_8, (hyb_launch<V, 1, 8, 64>))
+#undef BLKV
 template <class V> void hyb_2_8(const Args &a) { hyb_launch<V, 2, 8>(a); }
 
 #define SELLV(B, U, P) \
@@ -1267,6 +1299,9 @@ const std::vector<Variant> &table(spmv_format f) {
         VP(SPMV_KERNEL_COO_SORTED, 1024, 16, 4, 1, coo_sorted_16),
         VN(SPMV_KERNEL_COO_SPLIT, 256, 4, 1, 4, coo_split_4),
         VN(SPMV_KERNEL_COO_SPLIT, 256, 8, 1, 4, coo_split_8),
+        VN(SPMV_KERNEL_COO, 64, 8, 1, 4, coo_b64_8), VN(SPMV_KERNEL_COO, 128, 4, 1, 4, coo_b128_4),
+        VN(SPMV_KERNEL_COO, 512, 4, 1, 4, coo_b512_4), VN(SPMV_KERNEL_COO, 1024, 4, 1, 4, coo_b1024_4),
+        VN(SPMV_KERNEL_COO, 1024, 2, 1, 2, coo_b1024_2),
     };
     static const std::vector<Variant> ell = {
         VN(SPMV_KERNEL_ELL, 256, 1, 1, 1, ell_1_1), VN(SPMV_KERNEL_ELL, 256, 1, 2, 1, ell_1_2),
@@ -1280,6 +1315,10 @@ const std::vector<Variant> &table(spmv_format f) {
         VN(SPMV_KERNEL_ELL, 256, 1, 8, 1, ell_1_8), VN(SPMV_KERNEL_ELL, 256, 2, 8, 2, ell_2_8),
         VN(SPMV_KERNEL_ELL, 256, 4, 4, 4, ell_4_4), VN(SPMV_KERNEL_ELL, 256, 4, 8, 4, ell_4_8),
         VN(SPMV_KERNEL_ELL, 256, 1, 4, 1, ell_1_4), VN(SPMV_KERNEL_ELL, 256, 2, 4, 2, ell_2_4),
+        VN(SPMV_KERNEL_ELL, 64, 4, 2, 4, ell_b64_4_2), VN(SPMV_KERNEL_ELL, 128, 4, 2, 4, ell_b128_4_2),
+        VN(SPMV_KERNEL_ELL, 512, 4, 2, 4, ell_b512_4_2), VN(SPMV_KERNEL_ELL, 1024, 4, 2, 4, ell_b1024_4_2),
+        VN(SPMV_KERNEL_ELL, 64, 2, 4, 2, ell_b64_2_4), VN(SPMV_KERNEL_ELL, 128, 2, 4, 2, ell_b128_2_4),
+        VN(SPMV_KERNEL_ELL, 512, 2, 4, 2, ell_b512_2_4), VN(SPMV_KERNEL_ELL, 1024, 2, 4, 2, ell_b1024_2_4),
     };
     static const std::vector<Variant> hyb = {
         VN(SPMV_KERNEL_HYB, 256, 1, 4, 1, hyb_1_4), VN(SPMV_KERNEL_HYB, 256, 1, 8, 1, hyb_1_8),
@@ -1288,6 +1327,10 @@ const std::vector<Variant> &table(spmv_format f) {
         Variant{{SPMV_KERNEL_HYB, 256, 1, 8, 1, 1, 1}, hyb_s1_8<float>, hyb_s1_8<double>},
         Variant{{SPMV_KERNEL_HYB, 256, 2, 8, 2, 1, 1}, hyb_s2_8<float>, hyb_s2_8<double>},
         Variant{{SPMV_KERNEL_HYB, 256, 2, 16, 2, 1, 1}, hyb_s2_16<float>, hyb_s2_16<double>},
+        VN(SPMV_KERNEL_HYB, 128, 2, 8, 2, hyb_b128_2_8), VN(SPMV_KERNEL_HYB, 512, 2, 8, 2, hyb_b512_2_8),
+        VN(SPMV_KERNEL_HYB, 1024, 2, 8, 2, hyb_b1024_2_8), VN(SPMV_KERNEL_HYB, 64, 1, 8, 1, hyb_b64_1_8),
+        VN(SPMV_KERNEL_HYB, 256, 4, 4, 4, hyb_4_4), VN(SPMV_KERNEL_HYB, 256, 4, 8, 4, hyb_4_8),
+        Variant{{SPMV_KERNEL_HYB, 256, 4, 8, 4, 1, 1}, hyb_s4_8<float>, hyb_s4_8<double>},
     };
     static const std::vector<Variant> sell = {
         VS(256, 1, 0, 1, sell_256_1_0), VS(256, 2, 0, 1, sell_256_2_0), VS(256, 4, 0, 1, sell_256_4_0),

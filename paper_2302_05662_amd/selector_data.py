@@ -19,10 +19,12 @@ Results go to an ``.npz`` file that is rewritten every ``save_every`` matrices;
 an interrupted collection resumes from it (seeds already present are skipped).
 
 Usage: python -m paper_2302_05662_amd.selector_data OUT.npz FIRST_SEED LAST_SEED [--with-powerlaw]
-       [--six] [--limit-s SECONDS]
+       [--six] [--interleave] [--limit-s SECONDS]
        python -m paper_2302_05662_amd.selector_data --energy OUT.npz FIRST LAST STEP [--limit-s S]
 (--with-powerlaw draws from the extended family set that adds the power law; --limit-s
-stops after that many seconds, the saved file resuming later.)
+stops after that many seconds, the saved file resuming later; --interleave takes the seeds
+round-robin over the four quarters of the range, so a partial collection holds held-out
+matrices too.)
 """
 from __future__ import annotations
 
@@ -177,14 +179,23 @@ def collect_energy(path, seeds, seconds=0.1, tune_reps=3, save_every=10, log=pri
     return rec
 
 
+def interleaved(seeds, parts=4):
+    """The seeds in round-robin order over `parts` contiguous ranges, so a collection
+    stopped early still holds every range (the last quarter of the selector seeds is the
+    held-out split)."""
+    n = len(seeds)
+    stride = max(1, n // parts)
+    return [seeds[i] for i in sorted(range(n), key=lambda i: (i % stride, i))]
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "--energy":
         # --energy OUT.npz FIRST LAST STEP [--limit-s SECONDS]
         out, first, last, step = sys.argv[2], int(sys.argv[3]), int(sys.argv[4]), int(sys.argv[5])
         opts = sys.argv[6:]
         limit = float(opts[opts.index("--limit-s") + 1]) if "--limit-s" in opts else None
-        collect_energy(out, list(range(first, last + 1, step)), log=lambda s: print(s, flush=True),
-                       limit_s=limit)
+        collect_energy(out, interleaved(list(range(first, last + 1, step))),
+                       log=lambda s: print(s, flush=True), limit_s=limit)
         sys.exit(0)
     out, first, last = sys.argv[1], int(sys.argv[2]), int(sys.argv[3])
     import synth as _synth
@@ -192,5 +203,6 @@ if __name__ == "__main__":
     opts = sys.argv[4:]
     fams = _synth.CFG5X_FAMILIES if "--with-powerlaw" in opts else None
     limit = float(opts[opts.index("--limit-s") + 1]) if "--limit-s" in opts else None
-    collect(out, list(range(first, last + 1)), log=lambda s: print(s, flush=True), families=fams,
-            six="--six" in opts, limit_s=limit)
+    seeds = list(range(first, last + 1))
+    collect(out, interleaved(seeds) if "--interleave" in opts else seeds,
+            log=lambda s: print(s, flush=True), families=fams, six="--six" in opts, limit_s=limit)

@@ -16,6 +16,11 @@ python -m paper_2302_05662_amd.selector_fit --six DATA6.npz trains the six-class
 fits the overhead-aware run-time model on it; it writes selector_model6.npy,
 selector_runtime.npy and selector_eval6.json.
 
+python -m paper_2302_05662_amd.selector_fit --energy ENERGY.npz trains the energy head (the
+six-class network on the least-energy format per matrix, collected with ``selector_data
+--energy``) and a power head, and scores them on the check pass; it writes
+selector_model6_energy.npy, selector_model6_power.npy and selector_eval_energy.json.
+
 python -m paper_2302_05662_amd.selector_fit --extended DATA.npz EXT.npz evaluates, on a
 set that adds the power-law family (seeds 7000-7599), the installed network and one
 retrained on both training splits; it writes selector_eval_extended.json and
@@ -253,7 +258,82 @@ def fit6(d, seed=5, epochs=200):
     return model.cpu().numpy(), rt, ev
 
 
+def fit_energy(d, latency_model=None, seed=5, epochs=200):
+    """Energy head: the six-class network trained on energy labels (the format with the
+    least board energy per SpMV in the label pass), scored on the check pass's energy,
+    beside the power objective (least average power) and the latency-trained network
+    used for energy. Energy per SpMV and MFLOPS per watt rank formats identically
+    (the flops are fixed per matrix), so one label set serves both."""
+    import torch
+
+    import paper_2302_05662_amd as S
+    import synth
+
+    train = (d["seed"] >= TRAIN_SEEDS[0]) & (d["seed"] <= TRAIN_SEEDS[1])
+    held = (d["seed"] >= HELDOUT_SEEDS[0]) & (d["seed"] <= HELDOUT_SEEDS[1])
+    F = d["feats"].astype(np.float32)
+    y = labels_of(d["e_label"])
+    yw = labels_of(d["w_label"])
+    yt = labels_of(d["t_label"])
+    n = int(train.sum())
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    applicable = np.isfinite(d["e_check"]).astype(np.uint8)
+
+    def train_on(labels):
+        return S.spmv_selector_train(dev(F[train]), dev(labels[train]),
+                                     dev(synth.glorot_params(seed, layers=(12, 64, 64, NF6))),
+                                     dev(synth.epoch_permutations(seed, n, epochs)), epochs=epochs)
+
+    def predict(model):
+        _, cls = S.spmv_selector_predict(model, dev(F), applicable=dev(applicable))
+        return cls.cpu().numpy()
+
+    model_e = train_on(y)
+    model_w = train_on(yw)
+    pe, pw = predict(model_e), predict(model_w)
+    ec, wc = d["e_check"][held], d["w_check"][held]
+    tc = d["ms_check"][held]
+    ev = {"train_matrices": n, "heldout_matrices": int(held.sum()),
+          "idle_watts_median": float(np.median(d["idle_w"])),
+          "energy_label_histogram_train": np.bincount(y[train], minlength=NF6).tolist(),
+          "energy_label_histogram_heldout": np.bincount(y[held], minlength=NF6).tolist(),
+          "power_label_histogram_heldout": np.bincount(yw[held], minlength=NF6).tolist(),
+          "energy_label_equals_latency_label": float(np.mean(y == yt)),
+          "energy": {"model_energy": scores(pe[held], ec),
+                     "heldout_accuracy": float(np.mean(pe[held] == y[held])),
+                     "always_csr": scores(np.zeros(int(held.sum()), np.int64), ec),
+                     "rule": scores(d["rule"][held].astype(np.int64), ec),
+                     "latency_labels": scores(yt[held], ec),
+                     "label_pass_on_check": scores(y[held], ec)},
+          "power": {"model_power": scores(pw[held], wc),
+                    "heldout_accuracy": float(np.mean(pw[held] == yw[held])),
+                    "always_csr": scores(np.zeros(int(held.sum()), np.int64), wc),
+                    "latency_labels": scores(yt[held], wc),
+                    "energy_model": scores(pe[held], wc)},
+          "latency_of_energy_choice": scores(pe[held], tc)}
+    if latency_model is not None:
+        pl = predict(torch.from_numpy(latency_model).cuda())
+        ev["energy"]["latency_model"] = scores(pl[held], ec)
+    # spread of power across formats on one matrix: the paper's observation that the
+    # format moves power even where latency barely moves
+    wl = np.where(np.isfinite(d["w_label"]), d["w_label"], np.nan)
+    spread = np.nanmax(wl, axis=1) / np.nanmin(wl, axis=1) - 1
+    ev["power_spread_across_formats_median"] = float(np.nanmedian(spread))
+    ev["power_spread_across_formats_p95"] = float(np.nanpercentile(spread, 95))
+    return model_e.cpu().numpy(), model_w.cpu().numpy(), ev
+
+
 if __name__ == "__main__":
+    if sys.argv[1] == "--energy":
+        lat = os.path.join(HERE, "selector_model6.npy")
+        model_e, model_w, ev = fit_energy(load([sys.argv[2]]),
+                                          np.load(lat) if os.path.exists(lat) else None)
+        np.save(os.path.join(HERE, "selector_model6_energy.npy"), model_e)
+        np.save(os.path.join(HERE, "selector_model6_power.npy"), model_w)
+        with open(os.path.join(HERE, "selector_eval_energy.json"), "w") as fh:
+            json.dump(ev, fh, indent=1)
+        print(json.dumps(ev, indent=1))
+        sys.exit(0)
     if sys.argv[1] == "--six":
         model, rt, ev = fit6(load([sys.argv[2]]))
         np.save(os.path.join(HERE, "selector_model6.npy"), model)
