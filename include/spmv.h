@@ -268,7 +268,7 @@ spmv_status spmv_stored_bytes(spmv_handle h, spmv_format f, int32_t variant, int
  * optimisation mode -- the format moves power and efficiency) ------------- */
 
 typedef struct spmv_energy_result {
-    double seconds;         /* interval between the two counter updates (firmware clock) */
+    double seconds;         /* interval between the two counter updates (host clock)    */
     double joules;          /* board energy over that interval                           */
     double watts;           /* joules / seconds: average board power under the load      */
     int64_t runs;           /* SpMVs enqueued between the two updates                    */
@@ -282,13 +282,30 @@ typedef struct spmv_energy_result {
  * to the current HIP device by PCI id): after a 0.1 s warm period, wait for a
  * counter update, keep running for at least `seconds`, wait for the next
  * update; both updates fall inside the busy period. y is overwritten. The
- * board power includes the idle draw (see spmv_idle_power).
+ * board power includes the idle draw (see spmv_idle_power). The interval is
+ * timed with the host clock at the two detections; one whose energy implies
+ * no power or more than 5 kW holds a bad reading and is measured again (three
+ * attempts).
  *   x, y: device pointers as for spmv_run. seconds in (0, 60]. out: host.
  * Errors: INVALID_ARG, NOT_CONVERTED, NOT_APPLICABLE (no energy counter for
  * this device, it did not advance, or the variant does not apply), HIP.
  * Synchronises `stream`; takes about seconds + 0.2 s. */
 spmv_status spmv_energy(spmv_handle h, spmv_format f, int32_t variant, const void *x, void *y,
                         double seconds, spmv_energy_result *out, void *stream);
+
+/* Several formats of one matrix in one sweep (the energy labels of a matrix):
+ * after a 0.1 s warm period and a counter update, formats[i] (variants[i], -1
+ * or variants NULL = the current variant) runs back to back until `seconds`
+ * have passed and the counter has moved again, and that update opens the next
+ * format's interval, so the sweep takes about `count` counter periods (about
+ * 1 s each on MI355X) instead of two per format. Runs of one format that spill
+ * past its closing update (batches of about 1 ms) count towards the next. An
+ * interval whose energy is inconsistent is measured again alone.
+ *   formats, variants: host int32[count], 1 <= count <= 64. out: host
+ *   spmv_energy_result[count]. Errors: as spmv_energy. Synchronises `stream`. */
+spmv_status spmv_energy_formats(spmv_handle h, int32_t count, const int32_t *formats,
+                                const int32_t *variants, const void *x, void *y, double seconds,
+                                spmv_energy_result *out, void *stream);
 
 /* Average board power over at least `seconds` between two counter updates,
  * with no work of this library (other work on the device counts).

@@ -1026,6 +1026,27 @@ void ell_ksplit_launch(const Args &a) {
     SPMV_CHECK_LAUNCH();
 }
 
+// HYB with its ELL part split over KS waves per row block (wide, short ELL parts,
+// e.g. HYB of a banded matrix, where the rule keeps every row in the ELL part).
+template <class V, int KS, int RPT, int ITEMS>
+void hyb_ksplit_launch(const Args &a) {
+    const spmv_matrix_s *h = a.h;
+    if (h->n_rows == 0) return;
+    if (h->hyb.K == 0) {  // no slots: the plain kernel writes y = beta * y
+        ell_arrays_launch<V, 1, 1>(h->n_rows, 0, h->hyb.pitch, h->hyb.ell_col.as<int32_t>(),
+                                   h->hyb.ell_val.as<V>(), a);
+    } else {
+        ell_ksplit_kernel<V, KS, RPT><<<grid_of(ceil_div(h->n_rows, RPT), 64), 64 * KS, 0, a.s>>>(
+            h->n_rows, h->hyb.K, h->hyb.pitch, h->hyb.ell_col.as<int32_t>(), h->hyb.ell_val.as<V>(),
+            (const V *)a.x, (V)a.alpha, (V)a.beta, (V *)a.y);
+        SPMV_CHECK_LAUNCH();
+    }
+    if (h->hyb.nnz_tail > 0)
+        coo_launch_impl<V, ITEMS, true>(h->hyb.nnz_tail, h->n_rows, h->hyb.tail_row.as<int32_t>(),
+                                        h->hyb.tail_col.as<int32_t>(), h->hyb.tail_val.as<V>(), a,
+                                        h->hyb.partials.as<double>());
+}
+
 template <class V, int RPT, int ITEMS, int BLOCK = 256>
 void hyb_launch(const Args &a) {
     const spmv_matrix_s *h = a.h;
@@ -1197,6 +1218,8 @@ template <class V> void hyb_2_4(const Args &a) { hyb_launch<V, 2, 4>(a); }
 template <class V> void hyb_4_4(const Args &a) { hyb_launch<V, 4, 4>(a); }
 template <class V> void hyb_4_8(const Args &a) { hyb_launch<V, 4, 8>(a); }
 template <class V> void hyb_s4_8(const Args &a) { hyb_sorted_launch<V, 4, 8>(a); }
+template <class V> void hyb_k4_2(const Args &a) { hyb_ksplit_launch<V, 4, 2, 8>(a); }
+template <class V> void hyb_k4_4(const Args &a) { hyb_ksplit_launch<V, 4, 4, 8>(a); }
 // the paper's thread-block-size knob on ELL, tiled COO and HYB's ELL part
 #define BLKV(name, call) \
     template <class V> void name(const Args &a) { call(a); }
@@ -1331,6 +1354,8 @@ const std::vector<Variant> &table(spmv_format f) {
         VN(SPMV_KERNEL_HYB, 1024, 2, 8, 2, hyb_b1024_2_8), VN(SPMV_KERNEL_HYB, 64, 1, 8, 1, hyb_b64_1_8),
         VN(SPMV_KERNEL_HYB, 256, 4, 4, 4, hyb_4_4), VN(SPMV_KERNEL_HYB, 256, 4, 8, 4, hyb_4_8),
         Variant{{SPMV_KERNEL_HYB, 256, 4, 8, 4, 1, 1}, hyb_s4_8<float>, hyb_s4_8<double>},
+        Variant{{SPMV_KERNEL_HYB, 256, 2, 8, 2, 0, 4}, hyb_k4_2<float>, hyb_k4_2<double>},
+        Variant{{SPMV_KERNEL_HYB, 256, 4, 8, 4, 0, 4}, hyb_k4_4<float>, hyb_k4_4<double>},
     };
     static const std::vector<Variant> sell = {
         VS(256, 1, 0, 1, sell_256_1_0), VS(256, 2, 0, 1, sell_256_2_0), VS(256, 4, 0, 1, sell_256_4_0),

@@ -117,10 +117,12 @@ FIELDS_ENERGY = ("seed", "family", "n_rows", "nnz", "feats", "variant", "t_label
                  "e_label", "w_label", "ms_label", "e_check", "w_check", "ms_check", "idle_w")
 
 
-def collect_energy(path, seeds, seconds=0.1, tune_reps=3, save_every=10, log=print, limit_s=None):
+def collect_energy(path, seeds, seconds=0.2, tune_reps=3, save_every=10, log=print, limit_s=None,
+                   check_from=6500):
     """Energy labels: per matrix, every format (of six) autotuned for time, then the
-    board energy and average power of its tuned variant run back to back
-    (``spmv_energy``), twice: a label pass and an independent check pass."""
+    board energy and average power of its tuned variant run back to back, all formats
+    in one counter sweep (``spmv_energy_formats``): a label pass, and on the held-out
+    seeds (>= check_from) an independent check pass used for scoring."""
     import torch
 
     import paper_2302_05662_amd as S
@@ -150,12 +152,17 @@ def collect_energy(path, seeds, seconds=0.1, tune_reps=3, save_every=10, log=pri
                     raise
                 continue
             variant[fmt], t_label[fmt] = S.spmv_tune(h, fmt, x, y, reps=tune_reps, flush=True)
-        idle = S.spmv_idle_power(seconds)
-        for tag in ("label", "check"):
-            for fmt in range(nf):
-                if variant[fmt] < 0:
-                    continue
-                r = S.spmv_energy(h, fmt, x, y, seconds=seconds)
+        if i % 25 == 0:  # the idle draw drifts slowly: measured every 25 matrices
+            idle = S.spmv_idle_power(seconds)
+        fmts = [f for f in range(nf) if variant[f] >= 0]
+        # the check pass (scoring only) is measured on the held-out matrices
+        tags = ("label", "check") if spec["seed"] >= check_from else ("label",)
+        for tag in tags:
+            # one sweep per pass, the formats in a rotated order so no format always
+            # follows the same one
+            order = fmts[len(rec["seed"]) % len(fmts):] + fmts[:len(rec["seed"]) % len(fmts)]
+            res = S.spmv_energy_formats(h, order, x, y, seconds=seconds)
+            for fmt, r in zip(order, res):
                 e[f"e_{tag}"][fmt] = r["joules_per_run"]
                 e[f"w_{tag}"][fmt] = r["watts"]
                 e[f"ms_{tag}"][fmt] = r["ms_per_run"]

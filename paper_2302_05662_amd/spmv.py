@@ -103,6 +103,8 @@ class spmv_energy_result(ctypes.Structure):
 _sig("spmv_energy", _I32, _P, _I32, _I32, _P, _P, ctypes.c_double,
      ctypes.POINTER(spmv_energy_result), _P)
 _sig("spmv_idle_power", _I32, ctypes.c_double, ctypes.POINTER(ctypes.c_double))
+_sig("spmv_energy_formats", _I32, _P, _I32, _P, _P, _P, _P, ctypes.c_double,
+     ctypes.POINTER(spmv_energy_result), _P)
 _sig("spmv_tune", _I32, _P, _I32, _P, _P, _I32, ctypes.c_int, ctypes.POINTER(_I32),
      ctypes.POINTER(_F), _P)
 _sig("spmv_stored_bytes", _I32, _P, _I32, _I32, ctypes.POINTER(_I64))
@@ -352,6 +354,22 @@ def spmv_energy(h: Handle, fmt: int, x, y, seconds=0.25, variant=-1, stream=None
     _check(_lib.spmv_energy(h.ptr, int(fmt), int(variant), px, py, float(seconds), ctypes.byref(r),
                             _stream_ptr(stream)), "spmv_energy")
     return {k: getattr(r, k) for k, _ in spmv_energy_result._fields_}
+
+
+def spmv_energy_formats(h: Handle, formats, x, y, seconds=0.2, variants=None, stream=None) -> list:
+    """spmv_energy of several formats in one sweep (one counter period per format)."""
+    px = _check_vector(x, h.n_cols, h, "x")
+    py = _check_vector(y, h.n_rows, h, "y")
+    f = np.ascontiguousarray(formats, dtype=np.int32)
+    v = None if variants is None else np.ascontiguousarray(variants, dtype=np.int32)
+    if v is not None and v.shape != f.shape:
+        raise ValueError("variants must match formats")
+    out = (spmv_energy_result * len(f))()
+    _check(_lib.spmv_energy_formats(h.ptr, int(len(f)), ctypes.c_void_p(f.ctypes.data),
+                                    ctypes.c_void_p(v.ctypes.data if v is not None else 0), px, py,
+                                    float(seconds), out, _stream_ptr(stream)),
+           "spmv_energy_formats")
+    return [{k: getattr(r, k) for k, _ in spmv_energy_result._fields_} for r in out]
 
 
 def spmv_idle_power(seconds=0.25) -> float:

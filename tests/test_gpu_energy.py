@@ -72,3 +72,21 @@ def test_energy_argument_errors(banded):
     h2 = S.spmv_create(m.n_rows, m.n_cols, m.row, m.col, v)
     with pytest.raises(S.SpmvError, match="NOT_CONVERTED"):
         S.spmv_energy(h2, S.SPMV_FMT_SELL, x, y, seconds=0.05)
+
+
+def test_energy_sweep_of_formats(banded):
+    m, v, h, x, y = banded
+    fmts = [S.SPMV_FMT_CSR, S.SPMV_FMT_ELL, S.SPMV_FMT_BELL]
+    for f in fmts:
+        S.spmv_convert(h, f)
+    res = S.spmv_energy_formats(h, fmts, x, y, seconds=0.05)
+    assert len(res) == len(fmts)
+    for f, r in zip(fmts, res):
+        assert r["runs"] > 0 and 20.0 < r["watts"] < 3000.0, (S.FORMAT_NAMES[f], r)
+        assert r["joules_per_run"] == pytest.approx(r["watts"] * r["ms_per_run"] * 1e-3, rel=1e-9)
+        warm = float(np.median(S.spmv_time(h, f, x, y, warmup=3, reps=20, flush=False)))
+        assert 0.5 * warm < r["ms_per_run"] < 2.0 * warm, (S.FORMAT_NAMES[f], r["ms_per_run"], warm)
+    with pytest.raises(S.SpmvError, match="INVALID_ARG"):
+        S.spmv_energy_formats(h, [9], x, y)
+    with pytest.raises(ValueError):
+        S.spmv_energy_formats(h, fmts, x, y, variants=[0])
