@@ -104,10 +104,13 @@ def kernel_symbols(fmt, info, dtype="float"):
         return [f"coo_tile_kernel<{dtype}, {b}, {l}, false>", f"coo_fixup<{dtype}, {b * l}, false>"]
     if info["kernel"] == "ell":
         return [f"ell_kernel<{dtype}, {b}, {l}, {u}>"]
-    if pp:  # HYB whose tail runs through the sorted-block COO kernel
-        return [f"ell_kernel<{dtype}, {b}, {l}, 4>", f"coo_sorted_kernel<{dtype}, {u}, "]
-    return [f"ell_kernel<{dtype}, {b}, {l}, 4>", f"coo_tile_kernel<{dtype}, {b}, {u}, true>",
-            f"coo_fixup<{dtype}, {b * u}, true>"]
+    # HYB: the ELL part (grouped, or slot-split over `ksplit` waves), then the tail
+    ell = (f"ell_ksplit_kernel<{dtype}, {info['ksplit']}, {l}>" if info.get("ksplit", 1) > 1
+           else f"ell_kernel<{dtype}, {b}, {l}, 4>")
+    if pp:  # the tail runs through the sorted-block COO kernel
+        return [ell, f"coo_sorted_kernel<{dtype}, {u}, "]
+    # the tiled tail kernel always runs 256-thread workgroups
+    return [ell, f"coo_tile_kernel<{dtype}, 256, {u}, true>", f"coo_fixup<{dtype}, {256 * u}, true>"]
 
 
 def trace_summary(trace_csv, bench_json):
@@ -404,6 +407,43 @@ def fp64_section(S, torch, synth, seeds):
             "timing": "sum over matrices of the best format's tuned cold median (not a timed step)"}
 
 
+ENERGY_EVAL_PATH = os.path.join(ROOT, "paper_2302_05662_amd", "selector_eval_energy.json")
+
+
+def energy_section(S, mats, names=("s2000_", "s2001_", "s2003_")):
+    """Board energy and average power of every tuned format on a banded, a random-column and
+    a stencil matrix (one counter sweep each, the formats in turn), beside the energy head's
+    held-out result when it has been trained."""
+    try:
+        idle = S.spmv_idle_power(0.2)
+    except S.SpmvError as err:  # no energy counter on this device
+        return {"unavailable": str(err)}
+    out = {"idle_watts": round(idle, 1), "matrices": {}, "unit": "uJ per SpMV, W, MFLOPS/W",
+           "method": "spmv_energy_formats: each format's tuned variant back to back for one "
+                     "board energy counter period (about 1 s), board power including idle"}
+    for e in mats:
+        if not e["name"].startswith(names):
+            continue
+        fmts = [f for f in range(NF) if np.isfinite(e["times"][f])]
+        res = S.spmv_energy_formats(e["h"], fmts, e["xd"], e["y"], seconds=0.2)
+        out["matrices"][e["name"]] = {
+            FMT_NAMES[f]: {"uJ": round(r["joules_per_run"] * 1e6, 2), "W": round(r["watts"], 1),
+                           "MFLOPS_per_W": round(r["mflops_per_watt"], 1),
+                           "us": round(r["ms_per_run"] * 1e3, 2)} for f, r in zip(fmts, res)}
+        best_e = min(fmts, key=lambda f: res[fmts.index(f)]["joules_per_run"])
+        best_w = min(fmts, key=lambda f: res[fmts.index(f)]["watts"])
+        out["matrices"][e["name"]]["least_energy"] = FMT_NAMES[best_e]
+        out["matrices"][e["name"]]["least_power"] = FMT_NAMES[best_w]
+        out["matrices"][e["name"]]["fastest"] = FMT_NAMES[e["fmt"]]
+    if os.path.exists(ENERGY_EVAL_PATH):
+        with open(ENERGY_EVAL_PATH) as fh:
+            ev = json.load(fh)
+        out["energy_head_heldout"] = {k: ev["energy"][k] for k in ("model_energy", "always_csr",
+                                                                   "latency_labels")}
+        out["power_head_heldout"] = ev["power"]["model_power"]
+    return out
+
+
 def batched_section(S, torch, synth, count):
     """256 uneven SpMVs: one persistent graph launch vs 256 eager launches vs a graph of them."""
     specs = synth.config4_specs()[:count]
@@ -630,6 +670,7 @@ def main():
         rates, power_law = ingest_unsorted(S, torch, synth, tune=plan is None)
         setup_rates.update(rates)
     fp64 = None if (args.no_fp64 or plan is not None) else fp64_section(S, torch, synth, seeds)
+    energy = None if args.kernels_only else energy_section(S, mats)
     batched = None if args.no_batched else batched_section(S, torch, synth,
                                                            args.batched_matrices)
 
@@ -874,6 +915,7 @@ def main():
         "setup_rates": setup_rates,
         "selector": selector,
         "batched": batched,
+        "energy": energy,
         "power_law": power_law,
         "fp64": fp64,
         "plan": [{"name": e["name"], "fmt": e["fmt"],

@@ -11,6 +11,10 @@ majority class.
 Usage: python -m paper_2302_05662_amd.selector_fit DATA.npz [DATA2.npz ...]
 writes selector_model.npy and selector_eval.json next to this file.
 
+python -m paper_2302_05662_amd.selector_fit --four-from-six DATA6.npz does the same on the
+first four formats of a six-format collection and writes that view as
+selector_data_mi355x.npz (one collection serves both networks).
+
 python -m paper_2302_05662_amd.selector_fit --six DATA6.npz trains the six-class network
 (SELL and BELL as classes 4 and 5) on a dataset collected with ``selector_data --six`` and
 fits the overhead-aware run-time model on it; it writes selector_model6.npy,
@@ -323,7 +327,26 @@ def fit_energy(d, latency_model=None, seed=5, epochs=200):
     return model_e.cpu().numpy(), model_w.cpu().numpy(), ev
 
 
+def four_of_six(d):
+    """The four-format view (CSR, COO, ELL, HYB) of a dataset collected with --six."""
+    keep = ("seed", "family", "n_rows", "nnz", "feats", "t_label", "t_check", "variant", "rule")
+    out = {k: d[k] for k in keep}
+    for k in ("t_label", "t_check", "variant"):
+        out[k] = np.ascontiguousarray(d[k][:, :4])
+    return out
+
+
 if __name__ == "__main__":
+    if sys.argv[1] == "--four-from-six":
+        # the installed 4-class network and its dataset, from the six-format collection
+        d4 = four_of_six(load([sys.argv[2]]))
+        np.savez(os.path.join(HERE, "selector_data_mi355x.npz"), **d4)
+        model, ev = fit(d4)
+        np.save(MODEL_PATH, model)
+        with open(EVAL_PATH, "w") as fh:
+            json.dump(ev, fh, indent=1)
+        print(json.dumps(ev, indent=1))
+        sys.exit(0)
     if sys.argv[1] == "--energy":
         lat = os.path.join(HERE, "selector_model6.npy")
         model_e, model_w, ev = fit_energy(load([sys.argv[2]]),

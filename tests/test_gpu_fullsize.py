@@ -1,10 +1,11 @@
 """Full-size parity of the configurations the benchmark times, on every row.
 
-* Three single-SpMV matrices at their real sizes in FP32, every compiled variant of
-  every format: the 936K-row banded matrix (seed 2000, where the packed-index
-  sorted blocks run), the 835K-row uniform random matrix with 50 entries per row
-  (seed 2021) and the 1.49M-row random matrix whose sorted blocks keep 16-bit
-  rows (seed 2009).
+* Five single-SpMV matrices at their real sizes in FP32, every compiled variant of
+  every format (CSR, COO, ELL, HYB, SELL, BELL): the 936K-row banded matrix (seed
+  2000, where the packed-index sorted blocks and BELL run), the 835K-row uniform
+  random matrix with 50 entries per row (seed 2021), the 1.49M-row random matrix
+  whose sorted blocks keep 16-bit rows (seed 2009), the 1.47M-row block-diagonal
+  matrix (seed 2002, BELL at 8x8) and the 1.37M-row 3-D stencil (seed 2003, SELL).
 * The 256-matrix batch (seeds 4000-4255, 3.6e8 entries) in one persistent launch,
   with the setting the autotuner picks and with the sorted-block tiling.
 
@@ -53,7 +54,7 @@ def _set_variant(h, fmt, var):
         return False
 
 
-@pytest.mark.parametrize("seed", [2000, 2021, 2009])
+@pytest.mark.parametrize("seed", [2000, 2021, 2009, 2002, 2003])
 def test_single_spmv_set_full_size_every_variant(seed):
     m = synth.config2_matrix(seed)
     print(f"[fullsize] {m.name} nnz={m.nnz} f32", flush=True)
@@ -65,12 +66,12 @@ def test_single_spmv_set_full_size_every_variant(seed):
     del coo
     xd = torch.from_numpy(x).cuda()
     fmts = [S.SPMV_FMT_CSR, S.SPMV_FMT_COO]
-    for fmt in (S.SPMV_FMT_ELL, S.SPMV_FMT_HYB):
+    for fmt in (S.SPMV_FMT_ELL, S.SPMV_FMT_HYB, S.SPMV_FMT_SELL, S.SPMV_FMT_BELL):
         try:
             S.spmv_convert(h, fmt)
             fmts.append(fmt)
         except S.SpmvError as e:
-            assert e.status == "NOT_APPLICABLE" and fmt == S.SPMV_FMT_ELL
+            assert e.status == "NOT_APPLICABLE" and fmt != S.SPMV_FMT_HYB
     cases = [(1.0, 0.0, None), (1.5, -0.5, synth.uniform_vector(m.n_rows, np.float32, [seed, 4]))]
     refs = [_reference(rp, m.col, v, x, a, b, y0) for a, b, y0 in cases]
     ran = 0

@@ -95,3 +95,36 @@ def test_extended_set_with_the_power_law_family():
     assert pl.sum() >= 20
     assert regrets["retrained"].mean() <= 0.05
     assert regrets["retrained"][pl].mean() < regrets["installed"][pl].mean()
+
+
+DATA6 = os.path.join(PKG, "selector_data6_mi355x.npz")
+MODEL6 = os.path.join(PKG, "selector_model6.npy")
+
+
+def test_six_format_dataset_and_network():
+    """The six-format collection (CSR, COO, ELL, HYB, SELL, BELL on the selector seeds) and
+    the 6-class network trained from it: the network's predictions, recomputed by the FP64
+    oracle, stay within 5% of the best on the held-out matrices and beat always-CSR, the
+    rule and the best of the four spec formats alone."""
+    d = dict(np.load(DATA6, allow_pickle=False))
+    assert d["feats"].shape == (2000, 12) and d["t_label"].shape == (2000, 6)
+    assert np.all(np.isfinite(d["t_label"][:, [0, 1, 3]]))
+    specs = synth.config5_specs(d["seed"][:8].tolist())
+    assert [s["family"] for s in specs] == d["family"][:8].tolist()
+    held = (d["seed"] >= 6500) & (d["seed"] <= 6999)
+    assert held.sum() == 500
+    t = d["t_check"][held]
+    app = np.isfinite(t)
+    model = np.load(MODEL6).astype(np.float64)
+    n6 = OM.n_params(6)
+    pred, _ = OM.predict(model[:n6], model[n6:n6 + 12], model[n6 + 12:n6 + 24], d["feats"][held],
+                         applicable=app)
+    r = _regret(pred, t)
+    best4 = np.argmin(np.where(np.isfinite(d["t_label"][held][:, :4]), d["t_label"][held][:, :4], np.inf),
+                      axis=1)
+    assert r.mean() <= 0.05
+    assert r.mean() < _regret(np.zeros(held.sum(), np.int64), t).mean()
+    assert r.mean() < _regret(d["rule"][held].astype(np.int64), t).mean()
+    assert r.mean() < _regret(best4, t).mean()
+    ev = json.load(open(os.path.join(PKG, "selector_eval6.json")))
+    assert abs(ev["model"]["mean_regret"] - r.mean()) < 0.01
