@@ -177,7 +177,8 @@ def counter_summary(fetch_csv, write_csv, bench_json, out_json):
         with open(out_json) as fh:
             old = json.load(fh)
         if old.get("kernel_source_hash") == d["kernel_source_hash"]:
-            d["kernels"].update(old.get("kernels", {}))
+            d = {**old, **{k: v for k, v in d.items() if k != "kernels"},
+                 "kernels": dict(old.get("kernels", {}))}
     d["kernels"][rf["kernel"]] = round(traffic)
     with open(out_json, "w") as fh:
         json.dump(d, fh, indent=1)
@@ -191,6 +192,64 @@ def counter_summary(fetch_csv, write_csv, bench_json, out_json):
     print(f"| HBM traffic per launch (scaled) | {traffic / 1e6:.1f} MB |")
     print(f"| algorithmic bytes per launch | {rf['bytes_per_launch'] / 1e6:.1f} MB |")
     print(f"| traffic / algorithmic | {traffic / rf['bytes_per_launch']:.3f} |")
+
+
+REQ_COUNTERS = ("TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum",
+                "TCC_EA0_RDREQ_sum")
+
+
+def request_summary(csv_path, bench_json, out_json):
+    """L2-to-memory read bytes of the roofline kernel by request size (32, 64 and 128 B),
+    from one rocprofv3 pass of the four TCC_EA0_RDREQ counters over a --copy-calibration
+    run; the calibration copy checks the formula against bytes known in advance."""
+    import csv
+
+    with open(bench_json) as fh:
+        line = [l for l in fh if l.startswith("{")][-1]
+    res = json.loads(line)
+    rf, mib = res["roofline"], res["copy_calibration_mib"]
+    sym, n = rf["kernel_symbol"], rf["launches"]
+    per = {}
+    with open(csv_path) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] in REQ_COUNTERS:
+                per.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"]})[r["Counter_Name"]] = \
+                    float(r["Counter_Value"])
+    ids = sorted(per)
+    kern = [per[i] for i in ids if sym in per[i]["name"]][-n:]
+    copy = [per[i] for i in ids if "copyBuffer" in per[i]["name"]][-3:]
+    if len(kern) != n or len(copy) != 3:
+        raise SystemExit(f"{csv_path}: {len(kern)} dispatches of {sym} (want {n}), {len(copy)} copies")
+
+    def bytes_of(d):
+        return (32 * d[REQ_COUNTERS[0]] + 64 * d[REQ_COUNTERS[1]] + 128 * d[REQ_COUNTERS[2]])
+
+    def mean(rows, f):
+        return sum(f(d) for d in rows) / len(rows)
+
+    kb, cb = mean(kern, bytes_of), mean(copy, bytes_of)
+    known = mib * 1024.0 * 1024.0
+    unclassified = mean(kern, lambda d: d[REQ_COUNTERS[3]] - d[REQ_COUNTERS[0]] - d[REQ_COUNTERS[1]]
+                        - d[REQ_COUNTERS[2]])
+    print(f"kernel: {sym} ({rf['kernel']}), {n} timed dispatches")
+    print("| quantity | value |")
+    print("|---|---|")
+    for c in REQ_COUNTERS:
+        print(f"| {c} per launch | {mean(kern, lambda d: d[c]):.0f} |")
+    print(f"| requests in none of the three sizes, per launch | {unclassified:.0f} |")
+    print(f"| read bytes by request size per launch (32/64/128 B) | {kb / 1e6:.1f} MB |")
+    print(f"| same formula on the {mib} MiB calibration copy | {cb / known:.4f} of the bytes read |")
+    print(f"| algorithmic bytes per launch | {rf['bytes_per_launch'] / 1e6:.1f} MB |")
+    print(f"| reads by request size / algorithmic bytes | {kb / rf['bytes_per_launch']:.3f} |")
+    d = {}
+    if os.path.exists(out_json):
+        with open(out_json) as fh:
+            d = json.load(fh)
+    d.setdefault("read_bytes_by_request_size", {})[rf["kernel"]] = round(kb)
+    d["read_bytes_by_request_size_copy_check"] = round(cb / known, 4)
+    with open(out_json, "w") as fh:
+        json.dump(d, fh, indent=1)
+        fh.write("\n")
 
 
 def cpu_model():
@@ -531,6 +590,9 @@ def main():
                     help="after the timed steps, copy MIB MiB three times (counter calibration)")
     ap.add_argument("--trace-summary", nargs=2, metavar=("KERNEL_TRACE_CSV", "BENCH_JSON"),
                     help="summarise a rocprofv3 kernel trace of a previous run and exit")
+    ap.add_argument("--request-summary", nargs=3, metavar=("RDREQ_CSV", "BENCH_JSON", "OUT_JSON"),
+                    help="L2 read bytes of the roofline kernel by request size from one rocprofv3 "
+                         "pass of the TCC_EA0_RDREQ counters; merges into OUT_JSON and exits")
     ap.add_argument("--counter-summary", nargs=4,
                     metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON", "OUT_JSON"),
                     help="HBM traffic of the roofline kernel from rocprofv3 FETCH_SIZE and "
@@ -543,6 +605,9 @@ def main():
         return
     if args.counter_summary:
         counter_summary(*args.counter_summary)
+        return
+    if args.request_summary:
+        request_summary(*args.request_summary)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the library "

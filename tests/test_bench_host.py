@@ -30,6 +30,16 @@ def test_kernel_symbols_name_every_family():
     assert bench.kernel_symbols(2, dict(base, kernel="ell", lanes=4, ksplit=4, pipelined=1)) == \
         ["ell_ksplit_kernel<float, 4, 4>"]
     assert len(bench.kernel_symbols(3, dict(base, kernel="hyb", lanes=2, unroll=4))) == 3
+    # HYB's tiled tail runs 256-thread workgroups whatever the ELL part's workgroup size
+    assert bench.kernel_symbols(3, dict(base, kernel="hyb", block=1024, lanes=2, unroll=8)) == \
+        ["ell_kernel<float, 1024, 2, 4>", "coo_tile_kernel<float, 256, 8, true>",
+         "coo_fixup<float, 2048, true>"]
+    # HYB with its ELL part split over 4 waves
+    assert bench.kernel_symbols(3, dict(base, kernel="hyb", lanes=4, unroll=8, ksplit=4))[0] == \
+        "ell_ksplit_kernel<float, 4, 4>"
+    assert bench.kernel_symbols(4, dict(base, kernel="sell", unroll=2, pipelined=1)) == \
+        ["sell_kernel<float, 256, 2, true, "]
+    assert bench.kernel_symbols(5, dict(base, kernel="bell")) == ["bell_kernel<float, "]
 
 
 def test_trace_summary_uses_the_last_timed_launches(tmp_path, capsys):
@@ -82,3 +92,36 @@ def test_counter_summary_scales_by_the_calibration_copy(tmp_path, capsys):
     assert t["kernels"]["csr_key"] == (2000.0 * 2.0 + 200.0) * 1024
     assert t["kernel_source_hash"] == bench.kernel_source_hash()
     assert "traffic / algorithmic" in capsys.readouterr().out
+
+
+def test_request_summary_prices_reads_by_request_size(tmp_path, capsys):
+    path = tmp_path / "req.csv"
+    fields = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    mib = 1
+    rows = []
+    disp = 0
+    # one tuning dispatch, then 2 timed dispatches: 10 x 32 B, 20 x 64 B, 30 x 128 B each
+    for k, (a, b, c) in enumerate([(1, 1, 1), (10, 20, 30), (10, 20, 30)]):
+        disp += 1
+        for name, v in zip(bench.REQ_COUNTERS, (a, b, c, a + b + c)):
+            rows.append((disp, "void spmv::k<float, 4>()", name, v))
+    for _ in range(3):  # the calibration copy: 1 MiB in 128-byte requests
+        disp += 1
+        for name, v in zip(bench.REQ_COUNTERS, (0, 0, 8192, 8192)):
+            rows.append((disp, "__amd_rocclr_copyBuffer", name, v))
+    with open(path, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(fields)
+        w.writerows(rows)
+    js = tmp_path / "b.json"
+    js.write_text(json.dumps({"roofline": {"kernel_symbol": "k<float, ", "launches": 2, "kernel": "k_f32",
+                                           "bytes_per_launch": 5000.0},
+                              "copy_calibration_mib": mib}) + "\n")
+    out = tmp_path / "traffic.json"
+    out.write_text(json.dumps({"kernel_source_hash": "x", "kernels": {"other": 1}}))
+    bench.request_summary(str(path), str(js), str(out))
+    d = json.loads(out.read_text())
+    assert d["read_bytes_by_request_size"]["k_f32"] == 10 * 32 + 20 * 64 + 30 * 128
+    assert d["read_bytes_by_request_size_copy_check"] == 1.0
+    assert d["kernels"] == {"other": 1}  # the other figures stay
+    assert "| requests in none of the three sizes, per launch | 0 |" in capsys.readouterr().out
