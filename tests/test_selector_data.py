@@ -128,3 +128,25 @@ def test_six_format_dataset_and_network():
     assert r.mean() < _regret(best4, t).mean()
     ev = json.load(open(os.path.join(PKG, "selector_eval6.json")))
     assert abs(ev["model"]["mean_regret"] - r.mean()) < 0.01
+
+
+def test_energy_heads_on_the_energy_labels():
+    """The energy and power heads (6-class networks trained on the least-energy and the
+    least-power format of each matrix, from the board energy counter): re-predicted by the
+    FP64 oracle on the 50 held-out matrices, each beats always-CSR on its own objective and
+    matches the committed evaluation."""
+    d = dict(np.load(os.path.join(PKG, "selector_energy_mi355x.npz"), allow_pickle=False))
+    ev = json.load(open(os.path.join(PKG, "selector_eval_energy.json")))
+    held = (d["seed"] >= 6500) & (d["seed"] <= 6999)
+    assert held.sum() == ev["heldout_matrices"] and (~held).sum() == ev["train_matrices"]
+    n6 = OM.n_params(6)
+    for head, objective, key in (("energy", "e_check", "model_energy"),
+                                 ("power", "w_check", "model_power")):
+        model = np.load(os.path.join(PKG, f"selector_model6_{head}.npy")).astype(np.float64)
+        t = d[objective][held]
+        assert np.all(np.isfinite(t[:, [0, 1, 3]])) and np.all(t[np.isfinite(t)] > 0)
+        pred, _ = OM.predict(model[:n6], model[n6:n6 + 12], model[n6 + 12:n6 + 24],
+                             d["feats"][held], applicable=np.isfinite(t))
+        r = _regret(pred, t)
+        assert abs(ev[head][key]["mean_regret"] - r.mean()) < 0.01
+        assert r.mean() < _regret(np.zeros(held.sum(), np.int64), t).mean()
