@@ -586,6 +586,9 @@ def main():
                          "instead of the fastest format: a per-kernel measurement for profiles")
     ap.add_argument("--plan", help="JSON of a previous run: reuse its format/variant per matrix "
                     "instead of tuning")
+    ap.add_argument("--roofline-kernel", metavar="KEY",
+                    help="report this kernel group (a previous run's roofline.kernel) as the "
+                         "roofline kernel, for counter runs under a profiler")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy MIB MiB three times (counter calibration)")
     ap.add_argument("--trace-summary", nargs=2, metavar=("KERNEL_TRACE_CSV", "BENCH_JSON"),
@@ -788,6 +791,9 @@ def main():
         g["warm_ms"] += warm[i]
         g["members"].append(i)
     dom_key = max(groups, key=lambda k: groups[k]["warm_ms"])
+    if args.roofline_kernel and args.roofline_kernel in groups:
+        # counter runs: the kernel the timed run found dominant (profilers reorder the shares)
+        dom_key = args.roofline_kernel
     dom = groups[dom_key]
     members = set(dom["members"])
 
@@ -835,7 +841,9 @@ def main():
         instances.append({"kernel_symbol": inst[a], "launches": (b - a) * args.steps,
                           "avg_launch_us": round(ms * 1e3 / ((b - a) * args.steps), 3),
                           "achieved": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4)})
-    if args.copy_calibration:
+    for e in mats:  # outputs of the last timed step, for the CPU leg's check
+        e["y_gpu"] = e["y"].cpu().numpy()
+    if args.copy_calibration:  # the run's last device work: three copies of known size
         src = torch.zeros(args.copy_calibration * 2**18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
@@ -843,8 +851,6 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     ms_per_step = wall * 1e3 / args.steps
-    for e in mats:  # outputs of the last timed step, for the CPU leg's check
-        e["y_gpu"] = e["y"].cpu().numpy()
 
     useful = sum(e["useful_bytes"] for e in mats)
     cold_dom_ms = sum(cold_med[id(e)] for e in mats[:n_dom])
