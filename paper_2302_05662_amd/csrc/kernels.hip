@@ -150,37 +150,21 @@ __global__ __launch_bounds__(BLOCK) void csr_stream_kernel(const int32_t *__rest
     const int64_t e0 = rp[r0], e1 = rp[r1];
     const int64_t base = e0 & ~int64_t(3);
     if (e1 - base <= CAP) {
-        // every group's col/val loads first, then the gathers, then the products, so a
-        // thread waits one load latency and one gather latency for its whole share
-        constexpr int G = CAP / (4 * BLOCK);
-        Pack<int32_t, 4> c[G];
-        Pack<V, 4> v[G];
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
+        for (int g = 0; g < CAP / (4 * BLOCK); ++g) {
             const int64_t q = base + (int64_t)(g * BLOCK + threadIdx.x) * 4;
             if (q < e1) {
-                c[g] = ld_i32<4>(col + q);
-                v[g] = ld_val<4>(val + q);
-            }
-        }
-        V xv[G][4];
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int64_t q = base + (int64_t)(g * BLOCK + threadIdx.x) * 4;
-            if (q < e1) {
+                const Pack<int32_t, 4> c = ld_i32<4>(col + q);
+                const Pack<V, 4> v = ld_val<4>(val + q);
+                V xv[4];
                 bool ok[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) ok[j] = q + j >= e0 && q + j < e1;
-                gather_x<V, 4>(x, c[g].v, ok, xv[g]);
-            }
-        }
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int64_t q = base + (int64_t)(g * BLOCK + threadIdx.x) * 4;
-            if (q < e1)
+                gather_x<V, 4>(x, c.v, ok, xv);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    s_p[q - base + j] = (double)v[g].v[j] * (double)xv[g][j];
+                    s_p[q - base + j] = (double)v.v[j] * (double)xv[j];
+            }
         }
         __syncthreads();
         // LP lanes per row (a power of two, block-uniform): lane q of a row adds its
