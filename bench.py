@@ -48,9 +48,15 @@ def format_bytes(fmt, n_rows, n_cols, nnz, vb, K=0, pitch=0, tail=0):
     return pitch * K * (vb + 4) + tail * (vb + 8) + xy
 
 
-def kernel_source_hash():
+def kernel_source_hash(kernel_key=None):
+    """Hash of the sources a kernel group is compiled from: the streaming and sorted-block
+    COO kernels live in panel.hip, every other SpMV kernel in kernels.hip; both include the
+    device helpers and the common header."""
+    files = ("kernels.hip", "panel.hip", "device.hpp", "common.hpp")
+    if kernel_key and kernel_key.startswith(("coo_sorted", "coo_panel")):
+        files = ("panel.hip", "device.hpp", "common.hpp")
     h = hashlib.sha256()
-    for f in ("kernels.hip", "panel.hip", "device.hpp", "common.hpp"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2302_05662_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -63,7 +69,7 @@ def load_traffic(kernel_key):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    if d.get("source_hash_by_kernel", {}).get(kernel_key) != kernel_source_hash(kernel_key):
         return None
     t = d.get("kernels", {}).get(kernel_key)
     return float(t) if t is not None else None
@@ -169,17 +175,20 @@ def counter_summary(fetch_csv, write_csv, bench_json, out_json):
     known_kib = mib * 1024.0
     fs, ws = known_kib / fetch_copy, known_kib / write_copy
     traffic = (fetch * fs + write * ws) * 1024.0
-    d = {"kernel_source_hash": kernel_source_hash(),
-         "note": "HBM bytes per launch over the timed steps: FETCH_SIZE x fetch scale + "
-                 "WRITE_SIZE x write scale (KiB x 1024)",
-         "fetch_scale": round(fs, 6), "write_scale": round(ws, 6), "kernels": {}}
-    if os.path.exists(out_json):  # other kernels' figures, taken on the same sources, stay
+    d = {"note": "HBM bytes per launch over the timed steps: FETCH_SIZE x fetch scale + "
+                 "WRITE_SIZE x write scale (KiB x 1024); each kernel's figure holds while the "
+                 "sources it is compiled from hash to source_hash_by_kernel",
+         "fetch_scale": round(fs, 6), "write_scale": round(ws, 6), "kernels": {},
+         "source_hash_by_kernel": {}}
+    if os.path.exists(out_json):  # the other kernels' figures stay
         with open(out_json) as fh:
             old = json.load(fh)
-        if old.get("kernel_source_hash") == d["kernel_source_hash"]:
-            d = {**old, **{k: v for k, v in d.items() if k != "kernels"},
-                 "kernels": dict(old.get("kernels", {}))}
+        d = {**old, **{k: v for k, v in d.items() if k not in ("kernels", "source_hash_by_kernel")},
+             "kernels": dict(old.get("kernels", {})),
+             "source_hash_by_kernel": dict(old.get("source_hash_by_kernel", {}))}
+        d.pop("kernel_source_hash", None)
     d["kernels"][rf["kernel"]] = round(traffic)
+    d["source_hash_by_kernel"][rf["kernel"]] = kernel_source_hash(rf["kernel"])
     with open(out_json, "w") as fh:
         json.dump(d, fh, indent=1)
         fh.write("\n")

@@ -90,7 +90,8 @@ def test_counter_summary_scales_by_the_calibration_copy(tmp_path, capsys):
     t = json.loads((tmp_path / "t.json").read_text())
     assert t["fetch_scale"] == 2.0 and t["write_scale"] == 1.0
     assert t["kernels"]["csr_key"] == (2000.0 * 2.0 + 200.0) * 1024
-    assert t["kernel_source_hash"] == bench.kernel_source_hash()
+    assert t["source_hash_by_kernel"]["csr_key"] == bench.kernel_source_hash("csr_key")
+    assert bench.kernel_source_hash("coo_sorted_kernel_f32") != bench.kernel_source_hash("csr_key")
     assert "traffic / algorithmic" in capsys.readouterr().out
 
 
