@@ -261,6 +261,34 @@ def request_summary(csv_path, bench_json, out_json):
         fh.write("\n")
 
 
+def pmc_summary(csv_path, bench_json):
+    """Per-launch means of every counter in a rocprofv3 --pmc CSV over the roofline kernel's
+    timed dispatches, and per stored entry for a one-matrix run (--seeds S)."""
+    import csv
+
+    with open(bench_json) as fh:
+        line = [l for l in fh if l.startswith("{")][-1]
+    res = json.loads(line)
+    rf = res["roofline"]
+    sym, n = rf["kernel_symbol"], rf["launches"]
+    per = {}
+    with open(csv_path) as fh:
+        for r in csv.DictReader(fh):
+            per.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"]})[r["Counter_Name"]] = \
+                float(r["Counter_Value"])
+    kern = [per[i] for i in sorted(per) if sym in per[i]["name"]][-n:]
+    if len(kern) != n:
+        raise SystemExit(f"{csv_path}: {len(kern)} dispatches of {sym} (want {n})")
+    nnz = res["config"]["total_nnz"] if res["config"]["matrices"] == 1 else None
+    print(f"kernel: {sym} ({rf['kernel']}), {n} timed dispatches"
+          + (f", {nnz} stored entries per launch" if nnz else ""))
+    print("| counter | per launch | per entry |")
+    print("|---|---|---|")
+    for c in sorted(k for k in kern[0] if k != "name"):
+        m = sum(d[c] for d in kern) / n
+        print(f"| {c} | {m:.4g} | {m / nnz:.4g} |" if nnz else f"| {c} | {m:.4g} | |")
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -605,6 +633,9 @@ def main():
     ap.add_argument("--request-summary", nargs=3, metavar=("RDREQ_CSV", "BENCH_JSON", "OUT_JSON"),
                     help="L2 read bytes of the roofline kernel by request size from one rocprofv3 "
                          "pass of the TCC_EA0_RDREQ counters; merges into OUT_JSON and exits")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("PMC_CSV", "BENCH_JSON"),
+                    help="per-launch means of the counters of a rocprofv3 --pmc run for the "
+                         "roofline kernel's timed dispatches, and exit")
     ap.add_argument("--counter-summary", nargs=4,
                     metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON", "OUT_JSON"),
                     help="HBM traffic of the roofline kernel from rocprofv3 FETCH_SIZE and "
@@ -620,6 +651,9 @@ def main():
         return
     if args.request_summary:
         request_summary(*args.request_summary)
+        return
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the library "
