@@ -521,7 +521,11 @@ def energy_section(S, mats, names=("s2000_", "s2001_", "s2003_")):
         if not e["name"].startswith(names):
             continue
         fmts = [f for f in range(NF) if np.isfinite(e["times"][f])]
-        res = S.spmv_energy_formats(e["h"], fmts, e["xd"], e["y"], seconds=0.2)
+        try:
+            res = S.spmv_energy_formats(e["h"], fmts, e["xd"], e["y"], seconds=0.2)
+        except S.SpmvError as err:  # a counter that stops advancing: reported, not fatal
+            out["matrices"][e["name"]] = {"unavailable": str(err)}
+            continue
         out["matrices"][e["name"]] = {
             FMT_NAMES[f]: {"uJ": round(r["joules_per_run"] * 1e6, 2), "W": round(r["watts"], 1),
                            "MFLOPS_per_W": round(r["mflops_per_watt"], 1),
