@@ -3,7 +3,8 @@
 A plain, slow, obviously correct reference of what the GPU library computes:
 COO ingest (sort, duplicate check, row pointers), the CSR / COO / ELL / HYB /
 SELL-C-sigma / BELL layouts, y = alpha*A*x + beta*y in FP64, the 12 sparsity features and the
-12-64-64-4 selector network (forward, gradient, Adam, training loop).
+12-64-64-C selector network, C = 4 or 6 classes (forward, gradient, Adam,
+training loop).
 
 Only the tests, the smoke check and the bench's CPU-baseline leg may import
 this package. It shares no code with ``paper_2302_05662_amd`` and imports
