@@ -328,6 +328,20 @@ def cpu_baseline(mats, budget_s, threads):
         checked += 1
         if not err <= 1e-5:
             raise SystemExit(f"{m['name']}: GPU y differs from the oracle (row error {err:.3g} > 1e-5)")
+    batch_rows, batch_worst = 0, 0.0
+    for c in BATCH_CHECKS:  # the batched launch's sampled rows
+        k = len(c["cols"])
+        rp = np.zeros(k + 1, np.int64)
+        np.cumsum([len(a) for a in c["cols"]], out=rp[1:])
+        col = np.concatenate(c["cols"]).astype(np.int64)
+        val = np.concatenate(c["vals"]).astype(np.float64)
+        x = c["x"].astype(np.float64)
+        y_ref, den = OS.spmv_rows(np.arange(k), rp, col, val, x, 1.0, 0.0, None)
+        err = OS.max_row_error(c["y"], y_ref, den)
+        batch_worst = max(batch_worst, err)
+        batch_rows += k
+        if not err <= 1e-5:
+            raise SystemExit(f"batched launch: GPU y differs from the oracle (row error {err:.3g})")
     if not names:
         return None
     tot_t = sum(t for _, t in names)
@@ -346,6 +360,8 @@ def cpu_baseline(mats, budget_s, threads):
             "gflops": round(2 * sum(mm["nnz"] for mm in mats[:len(names)]) / tot_t / 1e9, 3),
             "single_thread_value": round(one_b / one_t / 1e9, 3),
             "checked_matrices": checked, "max_row_error_vs_gpu": float(f"{worst:.3g}"),
+            "checked_batched_rows": batch_rows,
+            "max_row_error_batched": float(f"{batch_worst:.3g}"),
             "sample": f"first {len(names)} of {len(mats)} matrices, FP64 CSR loop (FP32 inputs "
                       f"promoted) on {threads} threads (the CPU share of this process), median "
                       f"of 5 runs each, same useful-byte formula; single_thread_value: first 2 "
@@ -544,6 +560,9 @@ def energy_section(S, mats, names=("s2000_", "s2001_", "s2003_")):
     return out
 
 
+BATCH_CHECKS = []  # sampled rows of the batched outputs, checked in the CPU leg
+
+
 def batched_section(S, torch, synth, count):
     """256 uneven SpMVs: one persistent graph launch vs 256 eager launches vs a graph of them."""
     specs = synth.config4_specs()[:count]
@@ -588,6 +607,23 @@ def batched_section(S, torch, synth, count):
             S.spmv_run(h, f, 1.0, x, 0.0, y)
 
     persistent = time_it(lambda: S.spmv_batch_run(b))
+    # rows of every matrix as the persistent launch left them (first, last, longest and five
+    # seeded ones), with their entries, for the CPU leg's check against the oracle
+    for y in ys:
+        y.fill_(float("nan"))
+    S.spmv_batch_run(b)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(4999)
+    for sp, x, y in zip(specs, xs, ys):
+        m = synth.config4_matrix(sp)
+        rp = np.zeros(m.n_rows + 1, np.int64)
+        np.cumsum(np.bincount(m.row, minlength=m.n_rows), out=rp[1:])
+        rows = np.unique(np.concatenate([[0, m.n_rows - 1, int(np.argmax(np.diff(rp)))],
+                                         rng.integers(0, m.n_rows, 5)]))
+        v = m.values(np.float32)
+        BATCH_CHECKS.append({"cols": [m.col[rp[r]:rp[r + 1]] for r in rows],
+                             "vals": [v[rp[r]:rp[r + 1]] for r in rows],
+                             "x": m.x(np.float32), "y": y.cpu().numpy()[rows]})
     eager_ms = time_it(eager)
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
