@@ -209,7 +209,7 @@ spmv_status spmv_convert(spmv_handle h, spmv_format f, int32_t param, void *stre
  *      ignores NaN or garbage in y. x and y must not overlap.
  *   alpha, beta: rounded to the handle's dtype.
  * Rows with no entries get y = beta * y (or 0 when beta == 0).
- * Errors: INVALID_ARG (NULL x/y with a nonzero dimension, x == y),
+ * Errors: INVALID_ARG (NULL x/y with a nonzero dimension, x and y overlap),
  *         NOT_CONVERTED, HIP (launch failure). */
 spmv_status spmv_run(spmv_handle h, spmv_format f, double alpha, const void *x, double beta,
                      void *y, void *stream);
@@ -240,6 +240,7 @@ spmv_status spmv_get_variant(spmv_handle h, spmv_format f, int32_t *idx);
  * `warmup` untimed runs, y = 1 * A * x + 0 * y. If flush != 0 every timed run
  * is preceded by a 1 GiB read sweep that evicts L2 and the Infinity Cache.
  * Each run is bracketed by a pair of HIP events on `stream`.
+ *   x, y: device pointers as for spmv_run (y is overwritten).
  *   out_ms: host pointer, float[reps], milliseconds per run.
  * Errors: INVALID_ARG, NOT_CONVERTED, OOM (flush buffer), HIP.
  * Synchronises `stream`. */
@@ -289,7 +290,8 @@ typedef struct spmv_energy_result {
  *   x, y: device pointers as for spmv_run. seconds in (0, 60]. out: host.
  * Errors: INVALID_ARG, NOT_CONVERTED, NOT_APPLICABLE (no energy counter for
  * this device, it did not advance, or the variant does not apply), HIP.
- * Synchronises `stream`; takes about seconds + 0.2 s. */
+ * Synchronises `stream`; takes about seconds + 0.1 s + up to two counter
+ * periods (about 1 s each on MI355X). */
 spmv_status spmv_energy(spmv_handle h, spmv_format f, int32_t variant, const void *x, void *y,
                         double seconds, spmv_energy_result *out, void *stream);
 

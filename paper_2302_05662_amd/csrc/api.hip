@@ -57,6 +57,19 @@ void check_runnable(const spmv_matrix_s *h, spmv_format f) {
     if (!format_built(h, f)) fail(SPMV_ERR_NOT_CONVERTED, "format %d not converted", (int)f);
 }
 
+// x (n_cols values) and y (n_rows values) are present where the matrix needs them
+// and their byte ranges are disjoint.
+void check_vectors(const spmv_matrix_s *h, const void *x, const void *y) {
+    if (h->n_cols > 0 && !x) fail(SPMV_ERR_INVALID_ARG, "x is NULL");
+    if (h->n_rows > 0 && !y) fail(SPMV_ERR_INVALID_ARG, "y is NULL");
+    if (x && y && h->n_rows > 0 && h->n_cols > 0) {
+        const size_t vs = dtype_size(h->dt);
+        const char *xb = (const char *)x, *xe = xb + (size_t)h->n_cols * vs;
+        const char *yb = (const char *)y, *ye = yb + (size_t)h->n_rows * vs;
+        if (xb < ye && yb < xe) fail(SPMV_ERR_INVALID_ARG, "x and y overlap");
+    }
+}
+
 void convert(spmv_matrix_s *h, spmv_format f, int32_t param, hipStream_t s) {
     switch (f) {
         case SPMV_FMT_CSR:
@@ -211,14 +224,7 @@ extern "C" spmv_status spmv_run(spmv_handle h, spmv_format f, double alpha, cons
                                 double beta, void *y, void *stream) {
     return guard([&] {
         check_runnable(h, f);
-        const size_t vs = dtype_size(h->dt);
-        if (h->n_cols > 0 && !x) fail(SPMV_ERR_INVALID_ARG, "x is NULL");
-        if (h->n_rows > 0 && !y) fail(SPMV_ERR_INVALID_ARG, "y is NULL");
-        if (x && y && h->n_rows > 0 && h->n_cols > 0) {
-            const char *xb = (const char *)x, *xe = xb + (size_t)h->n_cols * vs;
-            const char *yb = (const char *)y, *ye = yb + (size_t)h->n_rows * vs;
-            if (xb < ye && yb < xe) fail(SPMV_ERR_INVALID_ARG, "x and y overlap");
-        }
+        check_vectors(h, x, y);
         launch_spmv(h, f, h->variant[f], alpha, x, beta, y, (hipStream_t)stream);
     });
 }

@@ -7,7 +7,7 @@
 // move latency (Results of the run-time optimisation mode).
 //
 // On MI355X the board exposes a monotone energy accumulator (amd-smi) that the
-// firmware advances every few tens of milliseconds. A measurement keeps the
+// firmware advances about once a second. A measurement keeps the
 // stream fed with batches of back-to-back runs, polls the counter until it
 // moves, keeps running for at least the asked duration and polls until it moves
 // again, so the interval between the two updates lies entirely inside the busy
@@ -194,6 +194,7 @@ double seconds_since(Clock::time_point t0) {
 }  // namespace
 
 void check_runnable(const spmv_matrix_s *h, spmv_format f);  // api.hip
+void check_vectors(const spmv_matrix_s *h, const void *x, const void *y);  // api.hip
 
 void measure_energy(spmv_matrix_s *h, spmv_format f, int32_t variant, const void *x, void *y,
                     double seconds, double warm_seconds, spmv_energy_result *out, hipStream_t s) {
@@ -362,8 +363,7 @@ extern "C" spmv_status spmv_energy(spmv_handle h, spmv_format f, int32_t variant
         check_runnable(h, f);
         if (!out) fail(SPMV_ERR_INVALID_ARG, "NULL result");
         if (!(seconds > 0.0) || seconds > 60.0) fail(SPMV_ERR_INVALID_ARG, "seconds must be in (0, 60]");
-        if ((h->n_cols > 0 && !x) || (h->n_rows > 0 && !y)) fail(SPMV_ERR_INVALID_ARG, "NULL x or y");
-        if (x == y && x) fail(SPMV_ERR_INVALID_ARG, "x and y alias");
+        check_vectors(h, x, y);
         const int32_t v = variant < 0 ? h->variant[f] : variant;
         if (v >= variant_count(f, h->dt)) fail(SPMV_ERR_INVALID_ARG, "variant %d out of range", v);
         if (!prepare_variant(h, f, v, (hipStream_t)stream))
@@ -379,8 +379,7 @@ extern "C" spmv_status spmv_energy_formats(spmv_handle h, int32_t count, const i
         if (!h || !formats || !out || count < 1 || count > 64)
             fail(SPMV_ERR_INVALID_ARG, "NULL argument or count outside [1, 64]");
         if (!(seconds > 0.0) || seconds > 60.0) fail(SPMV_ERR_INVALID_ARG, "seconds must be in (0, 60]");
-        if ((h->n_cols > 0 && !x) || (h->n_rows > 0 && !y)) fail(SPMV_ERR_INVALID_ARG, "NULL x or y");
-        if (x == y && x) fail(SPMV_ERR_INVALID_ARG, "x and y alias");
+        check_vectors(h, x, y);
         std::vector<spmv_format> fmts(count);
         std::vector<int32_t> vars(count);
         for (int32_t i = 0; i < count; ++i) {

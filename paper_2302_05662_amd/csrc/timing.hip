@@ -83,6 +83,7 @@ void flush_caches(hipStream_t s) {
 }
 
 void check_runnable(const spmv_matrix_s *h, spmv_format f);  // api.hip
+void check_vectors(const spmv_matrix_s *h, const void *x, const void *y);  // api.hip
 
 std::vector<float> time_runs(spmv_matrix_s *h, spmv_format f, int32_t variant, const void *x,
                              void *y, int32_t warmup, int32_t reps, int flush, hipStream_t s) {
@@ -138,7 +139,7 @@ extern "C" spmv_status spmv_time(spmv_handle h, spmv_format f, int32_t variant, 
         check_runnable(h, f);
         if (warmup < 0 || reps < 0 || (reps > 0 && !out_ms))
             fail(SPMV_ERR_INVALID_ARG, "bad warmup/reps/out_ms");
-        if ((h->n_cols > 0 && !x) || (h->n_rows > 0 && !y)) fail(SPMV_ERR_INVALID_ARG, "NULL x or y");
+        check_vectors(h, x, y);
         const int32_t v = variant < 0 ? h->variant[f] : variant;
         if (v >= variant_count(f, h->dt)) fail(SPMV_ERR_INVALID_ARG, "variant %d out of range", v);
         if (!prepare_variant(h, f, v, (hipStream_t)stream))
@@ -153,7 +154,7 @@ extern "C" spmv_status spmv_tune(spmv_handle h, spmv_format f, const void *x, vo
     return guard([&] {
         check_runnable(h, f);
         if (reps <= 0) fail(SPMV_ERR_INVALID_ARG, "reps must be positive");
-        if ((h->n_cols > 0 && !x) || (h->n_rows > 0 && !y)) fail(SPMV_ERR_INVALID_ARG, "NULL x or y");
+        check_vectors(h, x, y);
         const double m = tune_format(h, f, x, y, reps, flush, best_idx, (hipStream_t)stream);
         if (best_ms) *best_ms = (float)m;
     });

@@ -175,6 +175,25 @@ def test_run_errors_and_failed_convert_keeps_formats():
     assert np.all(np.isfinite(y.cpu().numpy())) and lengths.max() > 1000
 
 
+def test_overlapping_x_and_y_are_refused_by_every_runner():
+    """x and y that share bytes (here one element of one buffer) are refused before
+    any launch by the run, timing, tuning and energy entry points alike."""
+    m = C.matrix("lap64")
+    h = S.spmv_create(m.n_rows, m.n_cols, *C.shuffled_input("lap64", np.float32))
+    buf = torch.zeros(m.n_rows + m.n_cols - 1, device="cuda")
+    x, y = buf[:m.n_cols], buf[m.n_cols - 1:]
+    calls = [lambda: S.spmv_run(h, S.SPMV_FMT_CSR, 1.0, x, 0.0, y),
+             lambda: S.spmv_time(h, S.SPMV_FMT_CSR, x, y, reps=1, flush=False),
+             lambda: S.spmv_tune(h, S.SPMV_FMT_CSR, x, y, reps=1, flush=False),
+             lambda: S.spmv_energy(h, S.SPMV_FMT_CSR, x, y, seconds=0.01)]
+    for call in calls:
+        with pytest.raises(S.SpmvError) as e:
+            call()
+        assert e.value.status == "INVALID_ARG" and "overlap" in str(e.value)
+    torch.cuda.synchronize()
+    assert float(buf.abs().sum()) == 0.0  # nothing ran
+
+
 def test_full_size_power_law_ingest_from_shuffled_input():
     """2M x 2M power-law matrix (about 32M entries) through the radix-sort path."""
     m = synth.config3_matrix()
