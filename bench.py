@@ -53,7 +53,7 @@ def kernel_source_hash(kernel_key=None):
     COO kernels live in panel.hip, every other SpMV kernel in kernels.hip; both include the
     device helpers and the common header."""
     files = ("kernels.hip", "panel.hip", "device.hpp", "common.hpp")
-    if kernel_key and kernel_key.startswith(("coo_sorted", "coo_panel")):
+    if kernel_key and kernel_key.startswith(("coo_sorted", "coo_panel", "coo_tiles")):
         files = ("panel.hip", "device.hpp", "common.hpp")
     h = hashlib.sha256()
     for f in files:
@@ -101,6 +101,9 @@ def kernel_symbols(fmt, info, dtype="float"):
         return [f"{name}<{dtype}, {b}, {l}, {u}>"]
     if info["kernel"] == "coo_panel":
         return [f"coo_panel_kernel<{dtype}, {l}>"]
+    if info["kernel"] == "coo_sorted" and info.get("ksplit", 1) > 1:
+        # column tiles, then the second half's row sums added to y
+        return [f"coo_tiles_kernel<{dtype}, {l}, ", f"sorted_tiles_combine<{dtype}>"]
     if info["kernel"] == "coo_sorted":
         # the third template argument (16-bit rows or packed) depends on the matrix
         return [f"coo_sorted_kernel<{dtype}, {l}, "]
@@ -119,22 +122,34 @@ def kernel_symbols(fmt, info, dtype="float"):
     return [ell, f"coo_tile_kernel<{dtype}, 256, {u}, true>", f"coo_fixup<{dtype}, {256 * u}, true>"]
 
 
+def roofline_symbols(rf):
+    """Name substrings of every kernel one launch of the roofline group runs (main first)."""
+    return rf.get("kernel_symbols") or [rf["kernel_symbol"]]
+
+
 def trace_summary(trace_csv, bench_json):
-    """Average duration of the roofline kernel over the timed launches, from a rocprofv3 kernel trace."""
+    """Average duration of the roofline kernel over the timed launches, from a rocprofv3 kernel trace.
+    A launch of several kernels counts the sum of their average durations."""
     import csv
 
     with open(bench_json) as fh:
         line = [l for l in fh if l.startswith("{")][-1]
     rf = json.loads(line)["roofline"]
-    sym, n = rf["kernel_symbol"], rf["launches"]
+    syms, n = roofline_symbols(rf), rf["launches"]
     with open(trace_csv) as fh:
-        rows = [r for r in csv.DictReader(fh) if sym in r["Kernel_Name"]]
-    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
-    timed = rows[-n:]
-    dur_us = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in timed]
-    avg = sum(dur_us) / len(dur_us)
-    print(f"kernel: {sym}")
-    print(f"dispatches in trace: {len(rows)}; timed-region dispatches used: {len(timed)}")
+        all_rows = list(csv.DictReader(fh))
+    avg = 0.0
+    for sym in syms:
+        rows = [r for r in all_rows if sym in r["Kernel_Name"]]
+        rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+        timed = rows[-n:]
+        dur_us = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in timed]
+        a = sum(dur_us) / len(dur_us)
+        avg += a
+        print(f"kernel: {sym}")
+        print(f"dispatches in trace: {len(rows)}; timed-region dispatches used: {len(timed)}")
+        if len(syms) > 1:
+            print(f"rocprofv3 average duration of this kernel over the timed launches: {a:.3f} us")
     print(f"rocprofv3 average duration over the timed launches: {avg:.3f} us")
     print(f"bench HIP-event average per launch: {rf['avg_launch_us']:.3f} us")
     print(f"algorithmic bytes per launch (mean): {rf['bytes_per_launch']:.0f}")
@@ -155,20 +170,24 @@ def counter_summary(fetch_csv, write_csv, bench_json, out_json):
         line = [l for l in fh if l.startswith("{")][-1]
     res = json.loads(line)
     rf, mib = res["roofline"], res["copy_calibration_mib"]
-    sym, n = rf["kernel_symbol"], rf["launches"]
+    syms, n = roofline_symbols(rf), rf["launches"]
+    sym = " + ".join(syms)
 
     def read(path, counter):
         with open(path) as fh:
             rows = [r for r in csv.DictReader(fh) if r["Counter_Name"] == counter]
         rows.sort(key=lambda r: int(r["Dispatch_Id"]))
-        kern = [float(r["Counter_Value"]) for r in rows if sym in r["Kernel_Name"]][-n:]
         copy = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]][-3:]
         if min(copy, default=0.0) < mib * 1024.0 / 4:
             raise SystemExit(f"{path}: the last device copies are not the {mib} MiB calibration")
-        if len(kern) != n or len(copy) != 3:
-            raise SystemExit(f"{path}: {len(kern)} dispatches of {sym} (want {n}), "
-                             f"{len(copy)} calibration copies (want 3)")
-        return sum(kern) / n, sum(copy) / 3
+        total = 0.0
+        for one in syms:  # a launch of several kernels: the sum of their means
+            kern = [float(r["Counter_Value"]) for r in rows if one in r["Kernel_Name"]][-n:]
+            if len(kern) != n or len(copy) != 3:
+                raise SystemExit(f"{path}: {len(kern)} dispatches of {one} (want {n}), "
+                                 f"{len(copy)} calibration copies (want 3)")
+            total += sum(kern) / n
+        return total, sum(copy) / 3
 
     fetch, fetch_copy = read(fetch_csv, "FETCH_SIZE")
     write, write_copy = read(write_csv, "WRITE_SIZE")
@@ -217,7 +236,8 @@ def request_summary(csv_path, bench_json, out_json):
         line = [l for l in fh if l.startswith("{")][-1]
     res = json.loads(line)
     rf, mib = res["roofline"], res["copy_calibration_mib"]
-    sym, n = rf["kernel_symbol"], rf["launches"]
+    syms, n = roofline_symbols(rf), rf["launches"]
+    sym = " + ".join(syms)
     per = {}
     with open(csv_path) as fh:
         for r in csv.DictReader(fh):
@@ -225,10 +245,13 @@ def request_summary(csv_path, bench_json, out_json):
                 per.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"]})[r["Counter_Name"]] = \
                     float(r["Counter_Value"])
     ids = sorted(per)
-    kern = [per[i] for i in ids if sym in per[i]["name"]][-n:]
+    by_sym = [[per[i] for i in ids if one in per[i]["name"]][-n:] for one in syms]
     copy = [per[i] for i in ids if "copyBuffer" in per[i]["name"]][-3:]
-    if len(kern) != n or len(copy) != 3:
-        raise SystemExit(f"{csv_path}: {len(kern)} dispatches of {sym} (want {n}), {len(copy)} copies")
+    if any(len(k) != n for k in by_sym) or len(copy) != 3:
+        raise SystemExit(f"{csv_path}: {[len(k) for k in by_sym]} dispatches of {syms} (want {n}), "
+                         f"{len(copy)} copies")
+    # one row per launch: the counters of its kernels added
+    kern = [{c: sum(k[j][c] for k in by_sym) for c in REQ_COUNTERS} for j in range(n)]
 
     def bytes_of(d):
         return (32 * d[REQ_COUNTERS[0]] + 64 * d[REQ_COUNTERS[1]] + 128 * d[REQ_COUNTERS[2]])
@@ -270,21 +293,24 @@ def pmc_summary(csv_path, bench_json):
         line = [l for l in fh if l.startswith("{")][-1]
     res = json.loads(line)
     rf = res["roofline"]
-    sym, n = rf["kernel_symbol"], rf["launches"]
+    syms, n = roofline_symbols(rf), rf["launches"]
+    sym = " + ".join(syms)
     per = {}
     with open(csv_path) as fh:
         for r in csv.DictReader(fh):
             per.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"]})[r["Counter_Name"]] = \
                 float(r["Counter_Value"])
-    kern = [per[i] for i in sorted(per) if sym in per[i]["name"]][-n:]
-    if len(kern) != n:
-        raise SystemExit(f"{csv_path}: {len(kern)} dispatches of {sym} (want {n})")
+    by_sym = [[per[i] for i in sorted(per) if one in per[i]["name"]][-n:] for one in syms]
+    if any(len(k) != n for k in by_sym):
+        raise SystemExit(f"{csv_path}: {[len(k) for k in by_sym]} dispatches of {syms} (want {n})")
+    names = [c for c in by_sym[0][0] if c != "name"]
+    kern = [{c: sum(k[j][c] for k in by_sym) for c in names} for j in range(n)]
     nnz = res["config"]["total_nnz"] if res["config"]["matrices"] == 1 else None
     print(f"kernel: {sym} ({rf['kernel']}), {n} timed dispatches"
           + (f", {nnz} stored entries per launch" if nnz else ""))
     print("| counter | per launch | per entry |")
     print("|---|---|---|")
-    for c in sorted(k for k in kern[0] if k != "name"):
+    for c in sorted(kern[0]):
         m = sum(d[c] for d in kern) / n
         print(f"| {c} | {m:.4g} | {m / nnz:.4g} |" if nnz else f"| {c} | {m:.4g} | |")
 
@@ -833,6 +859,8 @@ def main():
         if len(syms) == 1:
             fn = syms[0].split("<")[0]
             return f"{fn}_f32", info, [f"{fn}<float, "]
+        if syms[0].startswith("coo_tiles_kernel<"):  # kernels no other variant runs
+            return "coo_tiles_kernel_f32", info, ["coo_tiles_kernel<float, ", syms[1]]
         key = (f"{info['kernel']}_b{info['block']}_l{info['lanes']}_u{info['unroll']}"
                f"_v{info['vec']}_p{info['pipelined']}_k{info['ksplit']}_f32")
         return key, info, syms
@@ -1048,6 +1076,7 @@ def main():
             "traffic": traffic,
             "share_of_kernel_time": round(dom["warm_ms"] / kernel_ms_per_step, 3),
             "kernel_symbol": dom["symbols"][0],
+            "kernel_symbols": dom["symbols"],
             "kernels_per_launch": len(dom["symbols"]),
             "launches": dom["launches"],
             "avg_launch_us": round(dom["ms"] * 1e3 / dom["launches"], 3),

@@ -81,7 +81,11 @@ typedef enum spmv_kernel {
                                    rows summed with LDS atomics across the block's
                                    16 waves: the order of the FP64 additions, and
                                    so the last bits of a result, may vary between
-                                   runs; second copy of the entries as above      */
+                                   runs; second copy of the entries as above;
+                                   ksplit = 2 (column tiles): blocks twice as tall,
+                                   each block's entries in two tiles by column
+                                   half, run by two workgroups; the second tile's
+                                   row sums are added to y by a second launch     */
     SPMV_KERNEL_COO_SPLIT = 7,  /* tiled COO run once per 2 MB column panel of x
                                    over a copy ordered by (panel, row, column), the
                                    first pass writing y, the others adding; only
@@ -124,7 +128,8 @@ typedef struct spmv_variant_info {
                           of rows each lane group walks as one stream, for ELL the
                           number of slots loaded ahead                            */
     int32_t ksplit;    /* ELL: waves of a workgroup sharing one block of rows, each
-                          taking every ksplit-th slot (1 = one thread per row)     */
+                          taking every ksplit-th slot (1 = one thread per row);
+                          sorted-block COO: column tiles per block of rows         */
 } spmv_variant_info;
 
 /* Borrowed view of a format's device arrays; valid until spmv_destroy or a

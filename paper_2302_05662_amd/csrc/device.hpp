@@ -307,12 +307,18 @@ constexpr int kSortedChunk = 256;
 
 typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
 
-template <class V, int ITEMS, int NW, bool ROW16>
+//
+// DELTA (column tiles): the packed index holds the column less the first column
+// of its chunk, chunk_base[chunk] (chunk = stream position / 256, clamped to
+// last_chunk like the loads), so a tall tile's row and column fit 32 bits.
+template <class V, int ITEMS, int NW, bool ROW16, bool DELTA = false>
 __device__ __forceinline__ void sorted_block_sum(const int32_t *__restrict__ idx,
                                                  const uint16_t *__restrict__ rows16,
                                                  const V *__restrict__ val,
                                                  const V *__restrict__ x, int64_t bs, int64_t be,
-                                                 int col_bits, int64_t last_load, double *s_y) {
+                                                 int col_bits, int64_t last_load, double *s_y,
+                                                 const int32_t *__restrict__ chunk_base = nullptr,
+                                                 int64_t last_chunk = 0) {
     static_assert(ITEMS % 4 == 0, "whole chunks per step");
     constexpr int SUB = ITEMS / 4;
     constexpr int CH = kSortedChunk * SUB;
@@ -327,6 +333,7 @@ __device__ __forceinline__ void sorted_block_sum(const int32_t *__restrict__ idx
         CI c[SUB];
         CV v[SUB];
         u16x4 r[SUB];
+        uint32_t base[SUB];
     };
     auto load = [&](int64_t q, Chunk &k) {
 #pragma unroll
@@ -335,6 +342,9 @@ __device__ __forceinline__ void sorted_block_sum(const int32_t *__restrict__ idx
             k.c[u] = ld_i32<4>(idx + e);
             k.v[u] = ld_val<4>(val + e);
             if constexpr (ROW16) k.r[u] = __builtin_nontemporal_load((const u16x4 *)(rows16 + e));
+            if constexpr (DELTA)
+                k.base[u] = (uint32_t)chunk_base[std::min<int64_t>((q + u * kSortedChunk) / kSortedChunk,
+                                                                   last_chunk)];
         }
     };
     auto step = [&](int64_t q, const Chunk &k, Chunk &kn) {
@@ -345,7 +355,8 @@ __device__ __forceinline__ void sorted_block_sum(const int32_t *__restrict__ idx
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 ok[u][j] = (q + u * kSortedChunk < end) && k.c[u].v[j] != -1;
-                const uint32_t col = ROW16 ? (uint32_t)k.c[u].v[j] : ((uint32_t)k.c[u].v[j] & col_mask);
+                uint32_t col = ROW16 ? (uint32_t)k.c[u].v[j] : ((uint32_t)k.c[u].v[j] & col_mask);
+                if constexpr (DELTA) col += k.base[u];
                 xv[u][j] = x[ok[u][j] ? col : 0u];
             }
         __builtin_amdgcn_sched_barrier(0);

@@ -1141,6 +1141,8 @@ void bell_launch(const Args &a) {
     Variant{{kind, blk, lanes, 1, vec, pipe, 1}, fn<float>, fn<double>}
 #define VK(kind, blk, rpt, ks, fn) \
     Variant{{kind, blk, rpt, 1, rpt, 1, ks}, fn<float>, fn<double>}
+#define VT(kind, blk, items, tiles, fn) \
+    Variant{{kind, blk, items, 1, 4, 1, tiles}, fn<float>, fn<double>}
 
 template <class V> void csr_s1(const Args &a) { csr_scalar_launch<V, 1>(a); }
 template <class V> void csr_s4(const Args &a) { csr_scalar_launch<V, 4>(a); }
@@ -1193,6 +1195,8 @@ template <class V> void coo_panel_8(const Args &a) { panel_spmv(a.h, 8, a.alpha,
 template <class V> void coo_sorted_4(const Args &a) { sorted_spmv(a.h, 4, a.alpha, a.x, a.beta, a.y, a.s); }
 template <class V> void coo_sorted_8(const Args &a) { sorted_spmv(a.h, 8, a.alpha, a.x, a.beta, a.y, a.s); }
 template <class V> void coo_sorted_16(const Args &a) { sorted_spmv(a.h, 16, a.alpha, a.x, a.beta, a.y, a.s); }
+template <class V> void coo_tiles_8(const Args &a) { sorted_tiles_spmv(a.h, 8, a.alpha, a.x, a.beta, a.y, a.s); }
+template <class V> void coo_tiles_16(const Args &a) { sorted_tiles_spmv(a.h, 16, a.alpha, a.x, a.beta, a.y, a.s); }
 template <class V> void coo_split_4(const Args &a) { coo_split_launch<V, 4>(a); }
 template <class V> void coo_split_8(const Args &a) { coo_split_launch<V, 8>(a); }
 template <class V> void csr_stream_256(const Args &a) { csr_stream_launch<V, 256>(a); }
@@ -1325,6 +1329,8 @@ const std::vector<Variant> &table(spmv_format f) {
         VN(SPMV_KERNEL_COO, 64, 8, 1, 4, coo_b64_8), VN(SPMV_KERNEL_COO, 128, 4, 1, 4, coo_b128_4),
         VN(SPMV_KERNEL_COO, 512, 4, 1, 4, coo_b512_4), VN(SPMV_KERNEL_COO, 1024, 4, 1, 4, coo_b1024_4),
         VN(SPMV_KERNEL_COO, 1024, 2, 1, 2, coo_b1024_2),
+        VT(SPMV_KERNEL_COO_SORTED, 1024, 8, 2, coo_tiles_8),
+        VT(SPMV_KERNEL_COO_SORTED, 1024, 16, 2, coo_tiles_16),
     };
     static const std::vector<Variant> ell = {
         VN(SPMV_KERNEL_ELL, 256, 1, 1, 1, ell_1_1), VN(SPMV_KERNEL_ELL, 256, 1, 2, 1, ell_1_2),
@@ -1457,7 +1463,15 @@ int64_t stored_bytes(const spmv_matrix_s *h, spmv_format f, int32_t idx) {
             if (!h->panel.built) return -1;
             return h->panel.stream * (4 + v) +
                    (ceil_div(n, std::max(h->panel.rows_per_wave, 1)) + 1) * 4;
-        case SPMV_KERNEL_COO_SORTED: return sorted_bytes(h->sorted);
+        case SPMV_KERNEL_COO_SORTED: {
+            if (info.ksplit == 1) return sorted_bytes(h->sorted);
+            const SortedPart &P = h->sorted_tiles;
+            if (!P.built) return -1;
+            // the tiles' streams and pointers, chunk bases, and the second half's
+            // row sums written and read back with y read and written again
+            return P.stream * (4 + v + (P.row16 ? 2 : 0)) + (P.delta ? P.stream / kSortedChunk * 4 : 0) +
+                   (int64_t)(P.blocks + 1) * 4 + 2 * (int64_t)(P.blocks * P.tiles + 1) * 4 + 4 * n * v;
+        }
         case SPMV_KERNEL_COO_SPLIT: {
             if (!h->split.built) return -1;
             int64_t e = 0;
@@ -1543,7 +1557,14 @@ bool variant_needs_hyb_sorted(spmv_format f, int32_t idx) {
 
 bool variant_needs_sorted(spmv_format f, int32_t idx) {
     const auto &t = table(f);
-    return idx >= 0 && idx < (int32_t)t.size() && t[idx].info.kernel == SPMV_KERNEL_COO_SORTED;
+    return idx >= 0 && idx < (int32_t)t.size() && t[idx].info.kernel == SPMV_KERNEL_COO_SORTED &&
+           t[idx].info.ksplit == 1;
+}
+
+bool variant_needs_sorted_tiles(spmv_format f, int32_t idx) {
+    const auto &t = table(f);
+    return idx >= 0 && idx < (int32_t)t.size() && t[idx].info.kernel == SPMV_KERNEL_COO_SORTED &&
+           t[idx].info.ksplit == 2;
 }
 
 void launch_spmv(const spmv_matrix_s *h, spmv_format f, int32_t variant, double alpha,

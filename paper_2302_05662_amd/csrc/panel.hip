@@ -317,6 +317,153 @@ void launch_sorted(const SortedPart &P, double alpha, const void *x, double beta
     SPMV_CHECK_LAUNCH();
 }
 
+// ---- column tiles of the sorted-block layout -------------------------------------
+
+// Workgroup i runs tile t = blk_order[i]: rows of block t / 2, entries of column
+// half t % 2. Tile 2b writes y = alpha * s + beta * y, tile 2b + 1 writes
+// alpha * s to partial (sorted_tiles_combine adds it afterwards).
+template <class V, int ITEMS, bool ROW16, bool DELTA>
+__global__ __launch_bounds__(kST) void coo_tiles_kernel(
+    const int32_t *__restrict__ blk_row, const int32_t *__restrict__ blk_order, int32_t col_bits,
+    const int32_t *__restrict__ blk_ptr, const int32_t *__restrict__ idx,
+    const uint16_t *__restrict__ rows16, const V *__restrict__ val, int64_t last_load,
+    const int32_t *__restrict__ chunk_base, int64_t last_chunk, const V *__restrict__ x, V alpha,
+    V beta, V *__restrict__ y, V *__restrict__ partial) {
+    __shared__ double s_y[kSortedRowsMax];
+    const int32_t t = blk_order[blockIdx.x];
+    const int32_t b = t >> 1;
+    const int64_t row0 = blk_row[b];
+    const int nr = blk_row[b + 1] - blk_row[b];
+    for (int i = threadIdx.x; i < nr; i += kST) s_y[i] = 0.0;
+    __syncthreads();
+    sorted_block_sum<V, ITEMS, kSortedWaves, ROW16, DELTA>(idx, rows16, val, x, blk_ptr[t],
+                                                           blk_ptr[t + 1], col_bits, last_load,
+                                                           s_y, chunk_base, last_chunk);
+    __syncthreads();
+    if ((t & 1) == 0) {
+        for (int i = threadIdx.x; i < nr; i += kST) store_y(y, row0 + i, s_y[i], alpha, beta);
+    } else {
+        for (int i = threadIdx.x; i < nr; i += kST)
+            partial[row0 + i] = (V)((double)alpha * s_y[i]);
+    }
+}
+
+// y += partial over all rows (the second column half's share).
+template <class V>
+__global__ void sorted_tiles_combine(int64_t n, const V *__restrict__ partial, V *__restrict__ y) {
+    for (int64_t r = (int64_t)blockIdx.x * kB + threadIdx.x; r < n; r += (int64_t)gridDim.x * kB)
+        y[r] = (V)((double)y[r] + (double)partial[r]);
+}
+
+// key = (tile << col_bits) | col, tile = 2 * block + (col >= split).
+__global__ void tiles_keys(const int32_t *__restrict__ row, const int32_t *__restrict__ col,
+                           int64_t nnz, const int32_t *__restrict__ blk_row, int32_t blocks,
+                           int32_t split, int32_t col_bits, uint64_t *__restrict__ key,
+                           uint32_t *__restrict__ perm) {
+    for (int64_t k = (int64_t)blockIdx.x * kB + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * kB) {
+        const int32_t b = sorted_block_of(blk_row, blocks, row[k]);
+        const uint64_t t = 2 * (uint64_t)b + (col[k] >= split ? 1 : 0);
+        key[k] = (t << col_bits) | (uint64_t)col[k];
+        perm[k] = (uint32_t)k;
+    }
+}
+
+// first[t] = sorted keys below tile t's first key (t = 0 .. tiles); padded[t] =
+// tile t's entries rounded up to whole chunks (padded[tiles] = 0).
+__global__ void tiles_first(const uint64_t *__restrict__ skey, int64_t nnz, int64_t tiles,
+                            int32_t col_bits, int32_t *__restrict__ first) {
+    for (int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x; t <= tiles;
+         t += (int64_t)gridDim.x * kB) {
+        const uint64_t want = (uint64_t)t << col_bits;
+        int64_t lo = 0, hi = nnz;  // first position whose key >= want
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (skey[mid] < want) lo = mid + 1; else hi = mid;
+        }
+        first[t] = (int32_t)lo;
+    }
+}
+
+__global__ void tiles_padded(const int32_t *__restrict__ first, int64_t tiles,
+                             int32_t *__restrict__ padded) {
+    for (int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x; t <= tiles;
+         t += (int64_t)gridDim.x * kB) {
+        const int64_t cnt = t < tiles ? first[t + 1] - first[t] : 0;
+        padded[t] = (int32_t)((cnt + kSortedChunk - 1) / kSortedChunk * kSortedChunk);
+    }
+}
+
+// Largest column span inside one chunk (last column less first) over all chunks.
+__global__ void tiles_span(const uint64_t *__restrict__ skey, int64_t nnz,
+                           const int32_t *__restrict__ first, int32_t col_bits,
+                           uint32_t *__restrict__ span) {
+    const uint64_t mask = (uint64_t(1) << col_bits) - 1;
+    uint32_t best = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * kB) {
+        const int64_t t = (int64_t)(skey[i] >> col_bits);
+        const int64_t k = i - first[t];
+        if (k % kSortedChunk != 0) continue;
+        const int64_t last = std::min<int64_t>(i + kSortedChunk, first[t + 1]) - 1;
+        best = std::max(best, (uint32_t)((skey[last] & mask) - (skey[i] & mask)));
+    }
+    if (best) atomicMax(span, best);
+}
+
+// Sorted position i goes to its tile's stream, transposed inside its chunk as in
+// sorted_scatter. delta: index = row inside the block << col_bits | (column less
+// the chunk's first column), and the chunk's first entry records that column;
+// otherwise index = column and the row goes to rows16.
+template <class V>
+__global__ void tiles_scatter(const uint64_t *__restrict__ skey, const uint32_t *__restrict__ perm,
+                              int64_t nnz, int32_t key_bits, const int32_t *__restrict__ row,
+                              const V *__restrict__ val, const int32_t *__restrict__ first,
+                              const int32_t *__restrict__ start,
+                              const int32_t *__restrict__ blk_row, bool delta, int32_t col_bits,
+                              int32_t *__restrict__ idx_out, uint16_t *__restrict__ rows16,
+                              int32_t *__restrict__ chunk_base, V *__restrict__ val_out) {
+    const uint64_t mask = (uint64_t(1) << key_bits) - 1;
+    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * kB) {
+        const uint32_t e = perm[i];
+        const int64_t t = (int64_t)(skey[i] >> key_bits);
+        const uint32_t c = (uint32_t)(skey[i] & mask);
+        const uint32_t rin = (uint32_t)(row[e] - blk_row[t >> 1]);
+        const int64_t k = i - first[t], rr = k % kSortedChunk;
+        const int64_t pos = (int64_t)start[t] + (k - rr) + (rr % kWave) * 4 + rr / kWave;
+        if (delta) {
+            const uint32_t c0 = (uint32_t)(skey[i - rr] & mask);
+            idx_out[pos] = (int32_t)((rin << col_bits) | (c - c0));
+            if (rr == 0) chunk_base[(start[t] + k) / kSortedChunk] = (int32_t)c;
+        } else {
+            idx_out[pos] = (int32_t)c;
+            rows16[pos] = (uint16_t)rin;
+        }
+        val_out[pos] = val[e];
+    }
+}
+
+template <class V, int ITEMS>
+void launch_tiles(const SortedPart &P, int64_t n_rows, double alpha, const void *x, double beta,
+                  void *y, hipStream_t s) {
+    const int64_t cap = padded_count(P.stream);
+    const int64_t last_chunk = std::max<int64_t>(P.stream / kSortedChunk - 1, 0);
+    const int32_t grid = P.blocks * P.tiles;
+    if (P.delta)
+        coo_tiles_kernel<V, ITEMS, false, true><<<grid, kST, 0, s>>>(
+            P.blk_row.as<int32_t>(), P.blk_order.as<int32_t>(), P.col_bits,
+            P.blk_ptr.as<int32_t>(), P.idx.as<int32_t>(), nullptr, P.val.as<V>(), cap - 4,
+            P.chunk_base.as<int32_t>(), last_chunk, (const V *)x, (V)alpha, (V)beta, (V *)y,
+            P.partial.as<V>());
+    else
+        coo_tiles_kernel<V, ITEMS, true, false><<<grid, kST, 0, s>>>(
+            P.blk_row.as<int32_t>(), P.blk_order.as<int32_t>(), P.col_bits,
+            P.blk_ptr.as<int32_t>(), P.idx.as<int32_t>(), P.rows16.as<uint16_t>(), P.val.as<V>(),
+            cap - 4, P.chunk_base.as<int32_t>(), last_chunk, (const V *)x, (V)alpha, (V)beta,
+            (V *)y, P.partial.as<V>());
+    SPMV_CHECK_LAUNCH();
+    sorted_tiles_combine<V><<<grid_of_n(n_rows), kB, 0, s>>>(n_rows, P.partial.as<V>(), (V *)y);
+    SPMV_CHECK_LAUNCH();
+}
+
 // ---- column-split COO ------------------------------------------------------------
 
 __global__ void split_keys(const int32_t *__restrict__ col, int64_t nnz, int32_t width,
@@ -591,6 +738,144 @@ void build_sorted_into(const spmv_matrix_s *h, const SortedEntries &src,
     P.blk_ptr = std::move(start);
     SPMV_HIP(hipStreamSynchronize(s));
     P.built = true;
+}
+
+void build_sorted_tiles(spmv_matrix_s *h, hipStream_t s) {
+    if (h->sorted_tiles.built) return;
+    (void)sorted_max_rows(h);
+    int cus = 0;
+    SPMV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
+    std::vector<int32_t> rp(h->n_rows + 1);
+    SPMV_HIP(hipMemcpyAsync(rp.data(), h->row_ptr.p, rp.size() * 4, hipMemcpyDeviceToHost, s));
+    SPMV_HIP(hipStreamSynchronize(s));
+    constexpr int T = 2;
+    // blocks for half the CUs: their two tiles fill every CU once
+    const std::vector<int32_t> row_start = sorted_balanced_rows(rp, kSortedRowsMax, std::max(cus / T, 1));
+    const int64_t n = h->n_rows, nnz = h->nnz, blocks = (int64_t)row_start.size() - 1;
+    const int64_t tiles = blocks * T;
+    int32_t tallest = 0;
+    for (int64_t b = 0; b < blocks; ++b) tallest = std::max(tallest, row_start[b + 1] - row_start[b]);
+    const int key_bits = sorted_col_bits(h);
+    const int32_t split = (h->n_cols + 1) / 2;
+    const size_t vs = dtype_size(h->dt);
+
+    SortedPart P;
+    P.tiles = T;
+    P.blocks = (int32_t)blocks;
+    P.rows = tallest;
+    P.row_start = row_start;
+    P.blk_row.alloc((blocks + 1) * 4);
+    SPMV_HIP(hipMemcpyAsync(P.blk_row.p, row_start.data(), (blocks + 1) * 4, hipMemcpyHostToDevice, s));
+
+    DevBuf keys, perm, first, start, span;
+    first.alloc((tiles + 1) * 4);
+    start.alloc((tiles + 1) * 4);
+    span.alloc(4);
+    keys.alloc(std::max<int64_t>(nnz, 1) * 8);
+    perm.alloc(std::max<int64_t>(nnz, 1) * 4);
+    SPMV_HIP(hipMemsetAsync(span.p, 0, 4, s));
+    if (nnz > 0) {
+        tiles_keys<<<grid_of_n(nnz), kB, 0, s>>>(h->row.as<int32_t>(), h->col.as<int32_t>(), nnz,
+                                                 P.blk_row.as<int32_t>(), P.blocks, split, key_bits,
+                                                 keys.as<uint64_t>(), perm.as<uint32_t>());
+        SPMV_CHECK_LAUNCH();
+        int bits = key_bits;
+        while (bits < 64 && (uint64_t)(tiles - 1) >> (bits - key_bits)) ++bits;
+        radix_sort_pairs(keys, perm, nnz, bits, s);
+    }
+    tiles_first<<<grid_of_n(tiles + 1), kB, 0, s>>>(keys.as<uint64_t>(), nnz, tiles, key_bits,
+                                                    first.as<int32_t>());
+    SPMV_CHECK_LAUNCH();
+    tiles_padded<<<grid_of_n(tiles + 1), kB, 0, s>>>(first.as<int32_t>(), tiles, start.as<int32_t>());
+    SPMV_CHECK_LAUNCH();
+    exclusive_scan_i32(start.as<int32_t>(), start.as<int32_t>(), tiles + 1, s);
+    if (nnz > 0) {
+        tiles_span<<<grid_of_n(nnz), kB, 0, s>>>(keys.as<uint64_t>(), nnz, first.as<int32_t>(),
+                                                 key_bits, span.as<uint32_t>());
+        SPMV_CHECK_LAUNCH();
+    }
+    int32_t total = 0;
+    uint32_t max_span = 0;
+    std::vector<int32_t> hfirst(tiles + 1);
+    SPMV_HIP(hipMemcpyAsync(&total, start.as<int32_t>() + tiles, 4, hipMemcpyDeviceToHost, s));
+    SPMV_HIP(hipMemcpyAsync(&max_span, span.p, 4, hipMemcpyDeviceToHost, s));
+    SPMV_HIP(hipMemcpyAsync(hfirst.data(), first.p, (tiles + 1) * 4, hipMemcpyDeviceToHost, s));
+    SPMV_HIP(hipStreamSynchronize(s));
+    // packed: row inside the block (tallest < 2^row_bits, so an index is never
+    // all ones, the padding mark) above the column less its chunk's first
+    int row_bits = 1;
+    while ((int64_t(1) << row_bits) <= tallest) ++row_bits;
+    const int delta_bits = 32 - row_bits;
+    P.delta = delta_bits > 0 && (uint64_t)max_span < (uint64_t(1) << delta_bits) - 1;
+    P.row16 = !P.delta;
+    P.col_bits = P.delta ? delta_bits : key_bits;
+    P.stream = total;
+
+    // workgroup order: tiles of column half 0 at positions whose XCD (position
+    // mod 8, as workgroups are dealt to the XCDs in turn) is 0-3, half 1 at 4-7,
+    // so each XCD's L2 serves one half of x; larger tiles first within a half
+    std::vector<int32_t> half[T];
+    for (int64_t t = 0; t < tiles; ++t) half[t % T].push_back((int32_t)t);
+    for (auto &v : half)
+        std::stable_sort(v.begin(), v.end(), [&](int32_t a, int32_t c) {
+            return hfirst[a + 1] - hfirst[a] > hfirst[c + 1] - hfirst[c];
+        });
+    std::vector<int32_t> order;
+    size_t take[T] = {0, 0};
+    for (int64_t w = 0; w < tiles; ++w) {
+        int hh = (w % 8) < 4 ? 0 : 1;
+        if (take[hh] == half[hh].size()) hh = 1 - hh;
+        order.push_back(half[hh][take[hh]++]);
+    }
+    P.blk_order.alloc(std::max<int64_t>(tiles, 1) * 4);
+    if (tiles > 0)
+        SPMV_HIP(hipMemcpyAsync(P.blk_order.p, order.data(), tiles * 4, hipMemcpyHostToDevice, s));
+
+    const int64_t cap = padded_count(total);
+    P.idx.alloc(cap * 4);
+    P.val.alloc(cap * vs);
+    P.chunk_base.alloc(std::max<int64_t>(total / kSortedChunk, 1) * 4);
+    P.partial.alloc(std::max<int64_t>(n, 1) * vs);
+    SPMV_HIP(hipMemsetAsync(P.idx.p, 0xFF, cap * 4, s));  // kPanelPad
+    SPMV_HIP(hipMemsetAsync(P.val.p, 0, cap * vs, s));
+    SPMV_HIP(hipMemsetAsync(P.chunk_base.p, 0, std::max<int64_t>(total / kSortedChunk, 1) * 4, s));
+    if (P.row16) {
+        P.rows16.alloc(cap * 2);
+        SPMV_HIP(hipMemsetAsync(P.rows16.p, 0, cap * 2, s));
+    }
+    if (nnz > 0) {
+        if (h->dt == SPMV_F64)
+            tiles_scatter<double><<<grid_of_n(nnz), kB, 0, s>>>(
+                keys.as<uint64_t>(), perm.as<uint32_t>(), nnz, key_bits, h->row.as<int32_t>(),
+                h->val.as<double>(), first.as<int32_t>(), start.as<int32_t>(),
+                P.blk_row.as<int32_t>(), P.delta, P.col_bits, P.idx.as<int32_t>(),
+                P.rows16.as<uint16_t>(), P.chunk_base.as<int32_t>(), P.val.as<double>());
+        else
+            tiles_scatter<float><<<grid_of_n(nnz), kB, 0, s>>>(
+                keys.as<uint64_t>(), perm.as<uint32_t>(), nnz, key_bits, h->row.as<int32_t>(),
+                h->val.as<float>(), first.as<int32_t>(), start.as<int32_t>(),
+                P.blk_row.as<int32_t>(), P.delta, P.col_bits, P.idx.as<int32_t>(),
+                P.rows16.as<uint16_t>(), P.chunk_base.as<int32_t>(), P.val.as<float>());
+        SPMV_CHECK_LAUNCH();
+    }
+    P.blk_ptr = std::move(start);
+    SPMV_HIP(hipStreamSynchronize(s));  // also keeps `order` alive until its copy is done
+    P.built = true;
+    h->sorted_tiles = std::move(P);
+}
+
+void sorted_tiles_spmv(const spmv_matrix_s *h, int items, double alpha, const void *x, double beta,
+                       void *y, hipStream_t s) {
+    if (!h->sorted_tiles.built) fail(SPMV_ERR_NOT_CONVERTED, "column-tile layout not built");
+    if (h->n_rows == 0) return;
+    const SortedPart &P = h->sorted_tiles;
+    if (h->dt == SPMV_F64) {
+        if (items == 8) launch_tiles<double, 8>(P, h->n_rows, alpha, x, beta, y, s);
+        else launch_tiles<double, 16>(P, h->n_rows, alpha, x, beta, y, s);
+    } else {
+        if (items == 8) launch_tiles<float, 8>(P, h->n_rows, alpha, x, beta, y, s);
+        else launch_tiles<float, 16>(P, h->n_rows, alpha, x, beta, y, s);
+    }
 }
 
 void sorted_spmv(const spmv_matrix_s *h, int items, double alpha, const void *x, double beta,

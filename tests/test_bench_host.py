@@ -40,6 +40,11 @@ def test_kernel_symbols_name_every_family():
     assert bench.kernel_symbols(4, dict(base, kernel="sell", unroll=2, pipelined=1)) == \
         ["sell_kernel<float, 256, 2, true, "]
     assert bench.kernel_symbols(5, dict(base, kernel="bell")) == ["bell_kernel<float, "]
+    # sorted-block COO in column tiles: the tile kernel, then the combine
+    assert bench.kernel_symbols(1, dict(base, kernel="coo_sorted", block=1024, lanes=16, ksplit=2)) == \
+        ["coo_tiles_kernel<float, 16, ", "sorted_tiles_combine<float>"]
+    assert bench.kernel_symbols(1, dict(base, kernel="coo_sorted", block=1024, lanes=16)) == \
+        ["coo_sorted_kernel<float, 16, "]
 
 
 def test_trace_summary_uses_the_last_timed_launches(tmp_path, capsys):
@@ -126,3 +131,28 @@ def test_request_summary_prices_reads_by_request_size(tmp_path, capsys):
     assert d["read_bytes_by_request_size_copy_check"] == 1.0
     assert d["kernels"] == {"other": 1}  # the other figures stay
     assert "| requests in none of the three sizes, per launch | 0 |" in capsys.readouterr().out
+
+
+def test_trace_summary_adds_the_kernels_of_one_launch(tmp_path, capsys):
+    """A roofline group whose launch runs two kernels: the per-launch duration is the sum of
+    the two kernels' averages over their last `launches` dispatches."""
+    trace = tmp_path / "t.csv"
+    with open(trace, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        t = 0
+        for i in range(5):  # 2 untimed then 3 timed launches: main 10/20 us, combine 2/3 us
+            for name, d in (("void spmv::coo_tiles_kernel<float, 8, false, true>(int)", 10000 if i < 2 else 20000),
+                            ("void spmv::sorted_tiles_combine<float>(long)", 2000 if i < 2 else 3000)):
+                w.writerow({"Kernel_Name": name, "Start_Timestamp": t, "End_Timestamp": t + d})
+                t += 100000
+    js = tmp_path / "b.json"
+    js.write_text(json.dumps({"roofline": {"kernel_symbol": "coo_tiles_kernel<float, ",
+                                           "kernel_symbols": ["coo_tiles_kernel<float, ",
+                                                              "sorted_tiles_combine<float>"],
+                                           "launches": 3, "avg_launch_us": 23.5,
+                                           "bytes_per_launch": 1e8, "achieved": 4255.3}}) + "\n")
+    bench.trace_summary(str(trace), str(js))
+    out = capsys.readouterr().out
+    assert "rocprofv3 average duration over the timed launches: 23.000 us" in out
+    assert "achieved from rocprofv3 duration: 4347.8 GB/s" in out
