@@ -256,6 +256,34 @@ def test_panel_variants_with_unaligned_x(dtype):
         assert OS.max_row_error(ga, y_ref, den) <= C.TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_column_tiles_with_unaligned_y(dtype):
+    """The column-tile variants add the second half's row sums into y with 16-byte
+    accesses when y allows them and one row at a time otherwise: y at an offset of one
+    value gives a result within the bound, and rows past y's end stay untouched."""
+    name = "random"
+    m = C.matrix(name)
+    print(f"[spmv tiles unaligned y] {name} {dtype.__name__}", flush=True)
+    h = _create(name, dtype)
+    x, y0 = C.vectors(name, dtype)
+    xd = torch.from_numpy(x).cuda()
+    a, b = C.ALPHA_BETA[1]
+    y_ref, den = C.reference(name, dtype, a, b)
+    tiles = [v for v in range(S.spmv_variant_count(S.SPMV_FMT_COO, h.dtype_code))
+             if S.spmv_variant_describe(S.SPMV_FMT_COO, h.dtype_code, v)["ksplit"] == 2]
+    assert tiles
+    for var in tiles:
+        S.spmv_set_variant(h, S.SPMV_FMT_COO, var)
+        buf = torch.full((m.n_rows + 2,), 7.0, dtype=xd.dtype, device="cuda")
+        buf[1:m.n_rows + 1] = torch.from_numpy(y0.copy()).cuda()
+        yu = buf[1:m.n_rows + 1]
+        assert yu.data_ptr() % 16 != 0
+        S.spmv_run(h, S.SPMV_FMT_COO, a, xd, b, yu)
+        g = buf.cpu().numpy()
+        assert g[0] == 7.0 and g[-1] == 7.0, var
+        assert OS.max_row_error(g[1:-1], y_ref, den) <= C.TOL[dtype], var
+
+
 def test_reordered_coo_layouts_at_their_column_limits():
     """Streaming COO packs columns in 23 bits and refuses wider matrices; sorted-block COO
     packs the row in the bits the column leaves free and still runs."""
