@@ -82,10 +82,12 @@ typedef enum spmv_kernel {
                                    16 waves: the order of the FP64 additions, and
                                    so the last bits of a result, may vary between
                                    runs; second copy of the entries as above;
-                                   ksplit = 2 (column tiles): blocks twice as tall,
-                                   each block's entries in two tiles by column
-                                   half, run by two workgroups; the second tile's
-                                   row sums are added to y by a second launch     */
+                                   ksplit = 2 or 4 (column tiles): blocks 2 or 4
+                                   times as tall, each block's entries in ksplit
+                                   tiles by column range, run by as many
+                                   workgroups; the other ranges' row sums are
+                                   added to y by a second launch (4 tiles apply
+                                   where one round of workgroups holds them)      */
     SPMV_KERNEL_COO_SPLIT = 7,  /* tiled COO run once per 2 MB column panel of x
                                    over a copy ordered by (panel, row, column), the
                                    first pass writing y, the others adding; only

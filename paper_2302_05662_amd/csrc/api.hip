@@ -156,7 +156,8 @@ bool prepare_variant(spmv_matrix_s *h, spmv_format f, int32_t idx, hipStream_t s
     try {
         if (variant_needs_panel(f, idx) && !h->panel.built) build_panel(h, s);
         if (variant_needs_sorted(f, idx) && !h->sorted.built) build_sorted(h, s);
-        if (variant_needs_sorted_tiles(f, idx) && !h->sorted_tiles.built) build_sorted_tiles(h, s);
+        if (const int T = variant_sorted_tiles(f, idx); T && !h->sorted_tiles[T == 4].built)
+            build_sorted_tiles(h, T, s);
         if (variant_needs_split(f, idx) && !h->split.built) build_split(h, s);
         if (variant_needs_csr_blocks(f, idx) && !h->csr_blocks.built) build_csr_blocks(h, s);
         if (variant_needs_hyb_sorted(f, idx) && !h->hyb_sorted.built) build_hyb_sorted(h, s);

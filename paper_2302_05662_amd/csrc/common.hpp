@@ -143,16 +143,17 @@ constexpr int kSortedWaves = 16;       // wavefronts per workgroup
 constexpr int kSortedRowsMax = 16384;  // rows per block at most (FP64 LDS accumulators)
 
 //
-// Column tiles (tiles = 2): each block's entries are split at the middle column
-// into two tiles, tile 2b + h holding block b's entries of column half h, each
-// its own stream of whole chunks (blk_ptr and blk_order count tiles). Blocks are
-// twice as tall as with one tile per block for the same number of workgroups,
-// so each workgroup gathers from half of x with twice the entries per line. A
-// tile's index packs the row inside the block above the column less the first
-// column of its chunk (delta; chunk_base[chunk]) when every chunk's column span
-// fits the bits left, else (row16) the index is the column. Tile 2b writes
-// y = alpha * s + beta * y for its rows, tile 2b + 1 writes alpha * s to
-// partial, and a second kernel adds partial to y.
+// Column tiles (tiles = T, 2 or 4): each block's entries are split into T tiles
+// by column range (width ceil(n_cols / T)), tile T b + h holding block b's
+// entries of range h, each its own stream of whole chunks (blk_ptr and
+// blk_order count tiles). Blocks are T times as tall as with one tile per block
+// for the same number of workgroups, so each workgroup gathers from 1/T of x
+// with T times the entries per line. A tile's index packs the row inside the
+// block above the column less the first column of its chunk (delta;
+// chunk_base[chunk]) when every chunk's column span fits the bits left, else
+// (row16) the index is the column. Tile T b writes y = alpha * s + beta * y for
+// its rows, tile T b + h (h > 0) writes alpha * s to partial[(h - 1) * pitch +
+// row], and a second kernel adds the T - 1 partial rows to y.
 struct SortedPart {
     bool built = false;
     bool row16 = false;
@@ -160,7 +161,7 @@ struct SortedPart {
     int32_t rows = 0;  // tallest block
     int32_t blocks = 0, col_bits = 0;
     int32_t tiles = 1;  // per block
-    int64_t stream = 0;
+    int64_t stream = 0, pitch = 0;  // pitch: rows per partial array
     std::vector<int32_t> row_start;  // host copy of blk_row
     DevBuf idx, val, blk_ptr, blk_row, blk_order, rows16, chunk_base, partial;
 };
@@ -236,7 +237,7 @@ struct spmv_matrix_s {
     spmv::PanelPart panel;    // built on first use of a streaming COO variant
     spmv::SortedPart sorted;  // built on first use of a sorted-block COO variant
     spmv::SortedPart hyb_sorted;  // the HYB tail's, built on first use of a sorted-tail HYB variant
-    spmv::SortedPart sorted_tiles;  // column-tile copy, built on first use of a column-tile variant
+    spmv::SortedPart sorted_tiles[2];  // column-tile copies ([0]: 2 tiles, [1]: 4), built on first use
     spmv::SplitPart split;    // built on first use of a column-split COO variant
     spmv::CsrBlocks csr_blocks;  // built on first use of a CSR stream variant
     spmv::SellPart sell;
@@ -302,10 +303,12 @@ void hyb_sorted_tail(const spmv_matrix_s *h, int items, double alpha, const void
 void build_split(spmv_matrix_s *h, hipStream_t s);  // NOT_APPLICABLE below two panels
 void sorted_spmv(const spmv_matrix_s *h, int items, double alpha, const void *x, double beta,
                  void *y, hipStream_t s);
-// Column-tile copy of the entries (h->sorted_tiles) and its SpMV (two launches).
-void build_sorted_tiles(spmv_matrix_s *h, hipStream_t s);
-void sorted_tiles_spmv(const spmv_matrix_s *h, int items, double alpha, const void *x, double beta,
-                       void *y, hipStream_t s);
+// Column-tile copy of the entries in `tiles` (2 or 4) tiles per block
+// (h->sorted_tiles[tiles == 4]) and its SpMV (two launches). Four tiles are
+// NOT_APPLICABLE where the blocks would need more than one round of workgroups.
+void build_sorted_tiles(spmv_matrix_s *h, int tiles, hipStream_t s);
+void sorted_tiles_spmv(const spmv_matrix_s *h, int tiles, int items, double alpha, const void *x,
+                       double beta, void *y, hipStream_t s);
 
 // kernels.hip
 int32_t variant_count(spmv_format f, spmv_dtype dt);
@@ -317,7 +320,7 @@ bool variant_applicable(const spmv_matrix_s *h, spmv_format f, int32_t idx);
 int64_t stored_bytes(const spmv_matrix_s *h, spmv_format f, int32_t idx);  // -1: not built
 bool variant_needs_panel(spmv_format f, int32_t idx);
 bool variant_needs_sorted(spmv_format f, int32_t idx);
-bool variant_needs_sorted_tiles(spmv_format f, int32_t idx);
+int variant_sorted_tiles(spmv_format f, int32_t idx);  // column tiles the variant needs, 0: none
 bool variant_needs_hyb_sorted(spmv_format f, int32_t idx);
 bool variant_needs_split(spmv_format f, int32_t idx);
 bool variant_needs_csr_blocks(spmv_format f, int32_t idx);

@@ -1195,8 +1195,10 @@ template <class V> void coo_panel_8(const Args &a) { panel_spmv(a.h, 8, a.alpha,
 template <class V> void coo_sorted_4(const Args &a) { sorted_spmv(a.h, 4, a.alpha, a.x, a.beta, a.y, a.s); }
 template <class V> void coo_sorted_8(const Args &a) { sorted_spmv(a.h, 8, a.alpha, a.x, a.beta, a.y, a.s); }
 template <class V> void coo_sorted_16(const Args &a) { sorted_spmv(a.h, 16, a.alpha, a.x, a.beta, a.y, a.s); }
-template <class V> void coo_tiles_8(const Args &a) { sorted_tiles_spmv(a.h, 8, a.alpha, a.x, a.beta, a.y, a.s); }
-template <class V> void coo_tiles_16(const Args &a) { sorted_tiles_spmv(a.h, 16, a.alpha, a.x, a.beta, a.y, a.s); }
+template <class V> void coo_tiles_8(const Args &a) { sorted_tiles_spmv(a.h, 2, 8, a.alpha, a.x, a.beta, a.y, a.s); }
+template <class V> void coo_tiles_16(const Args &a) { sorted_tiles_spmv(a.h, 2, 16, a.alpha, a.x, a.beta, a.y, a.s); }
+template <class V> void coo_tiles4_8(const Args &a) { sorted_tiles_spmv(a.h, 4, 8, a.alpha, a.x, a.beta, a.y, a.s); }
+template <class V> void coo_tiles4_16(const Args &a) { sorted_tiles_spmv(a.h, 4, 16, a.alpha, a.x, a.beta, a.y, a.s); }
 template <class V> void coo_split_4(const Args &a) { coo_split_launch<V, 4>(a); }
 template <class V> void coo_split_8(const Args &a) { coo_split_launch<V, 8>(a); }
 template <class V> void csr_stream_256(const Args &a) { csr_stream_launch<V, 256>(a); }
@@ -1331,6 +1333,8 @@ const std::vector<Variant> &table(spmv_format f) {
         VN(SPMV_KERNEL_COO, 1024, 2, 1, 2, coo_b1024_2),
         VT(SPMV_KERNEL_COO_SORTED, 1024, 8, 2, coo_tiles_8),
         VT(SPMV_KERNEL_COO_SORTED, 1024, 16, 2, coo_tiles_16),
+        VT(SPMV_KERNEL_COO_SORTED, 1024, 8, 4, coo_tiles4_8),
+        VT(SPMV_KERNEL_COO_SORTED, 1024, 16, 4, coo_tiles4_16),
     };
     static const std::vector<Variant> ell = {
         VN(SPMV_KERNEL_ELL, 256, 1, 1, 1, ell_1_1), VN(SPMV_KERNEL_ELL, 256, 1, 2, 1, ell_1_2),
@@ -1465,12 +1469,13 @@ int64_t stored_bytes(const spmv_matrix_s *h, spmv_format f, int32_t idx) {
                    (ceil_div(n, std::max(h->panel.rows_per_wave, 1)) + 1) * 4;
         case SPMV_KERNEL_COO_SORTED: {
             if (info.ksplit == 1) return sorted_bytes(h->sorted);
-            const SortedPart &P = h->sorted_tiles;
+            const SortedPart &P = h->sorted_tiles[info.ksplit == 4];
             if (!P.built) return -1;
-            // the tiles' streams and pointers, chunk bases, and the second half's
+            // the tiles' streams and pointers, chunk bases, and the other ranges'
             // row sums written and read back with y read and written again
             return P.stream * (4 + v + (P.row16 ? 2 : 0)) + (P.delta ? P.stream / kSortedChunk * 4 : 0) +
-                   (int64_t)(P.blocks + 1) * 4 + 2 * (int64_t)(P.blocks * P.tiles + 1) * 4 + 4 * n * v;
+                   (int64_t)(P.blocks + 1) * 4 + 2 * (int64_t)(P.blocks * P.tiles + 1) * 4 +
+                   2 * (int64_t)(P.tiles - 1) * n * v + 2 * n * v;
         }
         case SPMV_KERNEL_COO_SPLIT: {
             if (!h->split.built) return -1;
@@ -1561,10 +1566,12 @@ bool variant_needs_sorted(spmv_format f, int32_t idx) {
            t[idx].info.ksplit == 1;
 }
 
-bool variant_needs_sorted_tiles(spmv_format f, int32_t idx) {
+int variant_sorted_tiles(spmv_format f, int32_t idx) {
     const auto &t = table(f);
     return idx >= 0 && idx < (int32_t)t.size() && t[idx].info.kernel == SPMV_KERNEL_COO_SORTED &&
-           t[idx].info.ksplit == 2;
+                   t[idx].info.ksplit > 1
+               ? t[idx].info.ksplit
+               : 0;
 }
 
 void launch_spmv(const spmv_matrix_s *h, spmv_format f, int32_t variant, double alpha,

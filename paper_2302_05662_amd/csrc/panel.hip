@@ -319,19 +319,20 @@ void launch_sorted(const SortedPart &P, double alpha, const void *x, double beta
 
 // ---- column tiles of the sorted-block layout -------------------------------------
 
-// Workgroup i runs tile t = blk_order[i]: rows of block t / 2, entries of column
-// half t % 2. Tile 2b writes y = alpha * s + beta * y, tile 2b + 1 writes
-// alpha * s to partial (sorted_tiles_combine adds it afterwards).
+// Workgroup i runs tile t = blk_order[i]: rows of block t >> tiles_log2, entries
+// of column range h = t mod 2^tiles_log2. Range 0 writes y = alpha * s + beta * y,
+// range h > 0 writes alpha * s to partial row h - 1 (sorted_tiles_combine adds
+// them afterwards).
 template <class V, int ITEMS, bool ROW16, bool DELTA>
 __global__ __launch_bounds__(kST) void coo_tiles_kernel(
     const int32_t *__restrict__ blk_row, const int32_t *__restrict__ blk_order, int32_t col_bits,
     const int32_t *__restrict__ blk_ptr, const int32_t *__restrict__ idx,
     const uint16_t *__restrict__ rows16, const V *__restrict__ val, int64_t last_load,
-    const int32_t *__restrict__ chunk_base, int64_t last_chunk, const V *__restrict__ x, V alpha,
-    V beta, V *__restrict__ y, V *__restrict__ partial) {
+    const int32_t *__restrict__ chunk_base, int64_t last_chunk, int32_t tiles_log2, int64_t pitch,
+    const V *__restrict__ x, V alpha, V beta, V *__restrict__ y, V *__restrict__ partial) {
     __shared__ double s_y[kSortedRowsMax];
     const int32_t t = blk_order[blockIdx.x];
-    const int32_t b = t >> 1;
+    const int32_t b = t >> tiles_log2, hh = t & ((1 << tiles_log2) - 1);
     const int64_t row0 = blk_row[b];
     const int nr = blk_row[b + 1] - blk_row[b];
     for (int i = threadIdx.x; i < nr; i += kST) s_y[i] = 0.0;
@@ -340,19 +341,21 @@ __global__ __launch_bounds__(kST) void coo_tiles_kernel(
                                                            blk_ptr[t + 1], col_bits, last_load,
                                                            s_y, chunk_base, last_chunk);
     __syncthreads();
-    if ((t & 1) == 0) {
+    if (hh == 0) {
         for (int i = threadIdx.x; i < nr; i += kST) store_y(y, row0 + i, s_y[i], alpha, beta);
     } else {
-        for (int i = threadIdx.x; i < nr; i += kST)
-            partial[row0 + i] = (V)((double)alpha * s_y[i]);
+        V *p = partial + (int64_t)(hh - 1) * pitch;
+        for (int i = threadIdx.x; i < nr; i += kST) p[row0 + i] = (V)((double)alpha * s_y[i]);
     }
 }
 
-// y += partial over all rows (the second column half's share). With y 16-byte
-// aligned (partial always is), a thread adds 16 bytes of rows at a time, and the
-// rows past the last whole group one by one.
+// y += the `parts` partial rows (the other column ranges' shares; partial h at
+// h * pitch, pitch a multiple of 64), summed in FP64 in range order. With y
+// 16-byte aligned (the partial rows always are), a thread adds 16 bytes of rows
+// at a time, and the rows past the last whole group one by one.
 template <class V>
-__global__ void sorted_tiles_combine(int64_t n, const V *__restrict__ partial, V *__restrict__ y) {
+__global__ void sorted_tiles_combine(int64_t n, int32_t parts, int64_t pitch,
+                                     const V *__restrict__ partial, V *__restrict__ y) {
     constexpr int W = 16 / sizeof(V);
     typedef V vec_t __attribute__((ext_vector_type(W)));
     const int64_t tid = (int64_t)blockIdx.x * kB + threadIdx.x, stride = (int64_t)gridDim.x * kB;
@@ -360,25 +363,37 @@ __global__ void sorted_tiles_combine(int64_t n, const V *__restrict__ partial, V
     if (((uintptr_t)y & 15) == 0) {
         const int64_t groups = n / W;
         for (int64_t g = tid; g < groups; g += stride) {
-            const vec_t p = *(const vec_t *)(partial + g * W);
-            vec_t v = *(const vec_t *)(y + g * W);
+            const vec_t v = *(const vec_t *)(y + g * W);
+            double acc[W];
 #pragma unroll
-            for (int j = 0; j < W; ++j) v[j] = (V)((double)v[j] + (double)p[j]);
-            *(vec_t *)(y + g * W) = v;
+            for (int j = 0; j < W; ++j) acc[j] = (double)v[j];
+            for (int h = 0; h < parts; ++h) {
+                const vec_t p = *(const vec_t *)(partial + h * pitch + g * W);
+#pragma unroll
+                for (int j = 0; j < W; ++j) acc[j] += (double)p[j];
+            }
+            vec_t out;
+#pragma unroll
+            for (int j = 0; j < W; ++j) out[j] = (V)acc[j];
+            *(vec_t *)(y + g * W) = out;
         }
         done = groups * W;
     }
-    for (int64_t r = done + tid; r < n; r += stride) y[r] = (V)((double)y[r] + (double)partial[r]);
+    for (int64_t r = done + tid; r < n; r += stride) {
+        double acc = (double)y[r];
+        for (int h = 0; h < parts; ++h) acc += (double)partial[h * pitch + r];
+        y[r] = (V)acc;
+    }
 }
 
-// key = (tile << col_bits) | col, tile = 2 * block + (col >= split).
+// key = (tile << col_bits) | col, tile = T * block + col / width.
 __global__ void tiles_keys(const int32_t *__restrict__ row, const int32_t *__restrict__ col,
                            int64_t nnz, const int32_t *__restrict__ blk_row, int32_t blocks,
-                           int32_t split, int32_t col_bits, uint64_t *__restrict__ key,
-                           uint32_t *__restrict__ perm) {
+                           int32_t tiles, int32_t width, int32_t col_bits,
+                           uint64_t *__restrict__ key, uint32_t *__restrict__ perm) {
     for (int64_t k = (int64_t)blockIdx.x * kB + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * kB) {
         const int32_t b = sorted_block_of(blk_row, blocks, row[k]);
-        const uint64_t t = 2 * (uint64_t)b + (col[k] >= split ? 1 : 0);
+        const uint64_t t = (uint64_t)tiles * (uint64_t)b + (uint64_t)(col[k] / width);
         key[k] = (t << col_bits) | (uint64_t)col[k];
         perm[k] = (uint32_t)k;
     }
@@ -434,15 +449,16 @@ __global__ void tiles_scatter(const uint64_t *__restrict__ skey, const uint32_t 
                               int64_t nnz, int32_t key_bits, const int32_t *__restrict__ row,
                               const V *__restrict__ val, const int32_t *__restrict__ first,
                               const int32_t *__restrict__ start,
-                              const int32_t *__restrict__ blk_row, bool delta, int32_t col_bits,
-                              int32_t *__restrict__ idx_out, uint16_t *__restrict__ rows16,
-                              int32_t *__restrict__ chunk_base, V *__restrict__ val_out) {
+                              const int32_t *__restrict__ blk_row, int32_t tiles_log2, bool delta,
+                              int32_t col_bits, int32_t *__restrict__ idx_out,
+                              uint16_t *__restrict__ rows16, int32_t *__restrict__ chunk_base,
+                              V *__restrict__ val_out) {
     const uint64_t mask = (uint64_t(1) << key_bits) - 1;
     for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * kB) {
         const uint32_t e = perm[i];
         const int64_t t = (int64_t)(skey[i] >> key_bits);
         const uint32_t c = (uint32_t)(skey[i] & mask);
-        const uint32_t rin = (uint32_t)(row[e] - blk_row[t >> 1]);
+        const uint32_t rin = (uint32_t)(row[e] - blk_row[t >> tiles_log2]);
         const int64_t k = i - first[t], rr = k % kSortedChunk;
         const int64_t pos = (int64_t)start[t] + (k - rr) + (rr % kWave) * 4 + rr / kWave;
         if (delta) {
@@ -463,21 +479,22 @@ void launch_tiles(const SortedPart &P, int64_t n_rows, double alpha, const void 
     const int64_t cap = padded_count(P.stream);
     const int64_t last_chunk = std::max<int64_t>(P.stream / kSortedChunk - 1, 0);
     const int32_t grid = P.blocks * P.tiles;
+    const int32_t tiles_log2 = P.tiles == 4 ? 2 : 1;
     if (P.delta)
         coo_tiles_kernel<V, ITEMS, false, true><<<grid, kST, 0, s>>>(
             P.blk_row.as<int32_t>(), P.blk_order.as<int32_t>(), P.col_bits,
             P.blk_ptr.as<int32_t>(), P.idx.as<int32_t>(), nullptr, P.val.as<V>(), cap - 4,
-            P.chunk_base.as<int32_t>(), last_chunk, (const V *)x, (V)alpha, (V)beta, (V *)y,
-            P.partial.as<V>());
+            P.chunk_base.as<int32_t>(), last_chunk, tiles_log2, P.pitch, (const V *)x, (V)alpha,
+            (V)beta, (V *)y, P.partial.as<V>());
     else
         coo_tiles_kernel<V, ITEMS, true, false><<<grid, kST, 0, s>>>(
             P.blk_row.as<int32_t>(), P.blk_order.as<int32_t>(), P.col_bits,
             P.blk_ptr.as<int32_t>(), P.idx.as<int32_t>(), P.rows16.as<uint16_t>(), P.val.as<V>(),
-            cap - 4, P.chunk_base.as<int32_t>(), last_chunk, (const V *)x, (V)alpha, (V)beta,
-            (V *)y, P.partial.as<V>());
+            cap - 4, P.chunk_base.as<int32_t>(), last_chunk, tiles_log2, P.pitch, (const V *)x,
+            (V)alpha, (V)beta, (V *)y, P.partial.as<V>());
     SPMV_CHECK_LAUNCH();
     sorted_tiles_combine<V><<<grid_of_n(ceil_div(n_rows, 16 / (int64_t)sizeof(V))), kB, 0, s>>>(
-        n_rows, P.partial.as<V>(), (V *)y);
+        n_rows, P.tiles - 1, P.pitch, P.partial.as<V>(), (V *)y);
     SPMV_CHECK_LAUNCH();
 }
 
@@ -757,27 +774,31 @@ void build_sorted_into(const spmv_matrix_s *h, const SortedEntries &src,
     P.built = true;
 }
 
-void build_sorted_tiles(spmv_matrix_s *h, hipStream_t s) {
-    if (h->sorted_tiles.built) return;
+void build_sorted_tiles(spmv_matrix_s *h, int T, hipStream_t s) {
+    if (T != 2 && T != 4) fail(SPMV_ERR_INVALID_ARG, "column tiles per block: 2 or 4, not %d", T);
+    if (h->sorted_tiles[T == 4].built) return;
     (void)sorted_max_rows(h);
     int cus = 0;
     SPMV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
     std::vector<int32_t> rp(h->n_rows + 1);
     SPMV_HIP(hipMemcpyAsync(rp.data(), h->row_ptr.p, rp.size() * 4, hipMemcpyDeviceToHost, s));
     SPMV_HIP(hipStreamSynchronize(s));
-    constexpr int T = 2;
-    // blocks for half the CUs: their two tiles fill every CU once
-    const std::vector<int32_t> row_start = sorted_balanced_rows(rp, kSortedRowsMax, std::max(cus / T, 1));
+    // blocks for 1/T of the CUs: their T tiles fill every CU once
+    const int per_round = std::max(cus / T, 1);
+    const std::vector<int32_t> row_start = sorted_balanced_rows(rp, kSortedRowsMax, per_round);
     const int64_t n = h->n_rows, nnz = h->nnz, blocks = (int64_t)row_start.size() - 1;
+    if (T == 4 && blocks > per_round)
+        fail(SPMV_ERR_NOT_APPLICABLE, "four column tiles need blocks of more than %d rows", kSortedRowsMax);
     const int64_t tiles = blocks * T;
     int32_t tallest = 0;
     for (int64_t b = 0; b < blocks; ++b) tallest = std::max(tallest, row_start[b + 1] - row_start[b]);
     const int key_bits = sorted_col_bits(h);
-    const int32_t split = (h->n_cols + 1) / 2;
+    const int32_t width = std::max<int32_t>((int32_t)ceil_div((int64_t)h->n_cols, T), 1);
     const size_t vs = dtype_size(h->dt);
 
     SortedPart P;
     P.tiles = T;
+    P.pitch = ceil_div(std::max<int64_t>(n, 1), 64) * 64;
     P.blocks = (int32_t)blocks;
     P.rows = tallest;
     P.row_start = row_start;
@@ -793,8 +814,8 @@ void build_sorted_tiles(spmv_matrix_s *h, hipStream_t s) {
     SPMV_HIP(hipMemsetAsync(span.p, 0, 4, s));
     if (nnz > 0) {
         tiles_keys<<<grid_of_n(nnz), kB, 0, s>>>(h->row.as<int32_t>(), h->col.as<int32_t>(), nnz,
-                                                 P.blk_row.as<int32_t>(), P.blocks, split, key_bits,
-                                                 keys.as<uint64_t>(), perm.as<uint32_t>());
+                                                 P.blk_row.as<int32_t>(), P.blocks, T, width,
+                                                 key_bits, keys.as<uint64_t>(), perm.as<uint32_t>());
         SPMV_CHECK_LAUNCH();
         int bits = key_bits;
         while (bits < 64 && (uint64_t)(tiles - 1) >> (bits - key_bits)) ++bits;
@@ -828,21 +849,21 @@ void build_sorted_tiles(spmv_matrix_s *h, hipStream_t s) {
     P.col_bits = P.delta ? delta_bits : key_bits;
     P.stream = total;
 
-    // workgroup order: tiles of column half 0 at positions whose XCD (position
-    // mod 8, as workgroups are dealt to the XCDs in turn) is 0-3, half 1 at 4-7,
-    // so each XCD's L2 serves one half of x; larger tiles first within a half
-    std::vector<int32_t> half[T];
-    for (int64_t t = 0; t < tiles; ++t) half[t % T].push_back((int32_t)t);
-    for (auto &v : half)
+    // workgroup order: tiles of column range h at positions whose XCD (position
+    // mod 8, as workgroups are dealt to the XCDs in turn) is in [8h/T, 8(h+1)/T),
+    // so each XCD's L2 serves one range of x; larger tiles first within a range
+    std::vector<std::vector<int32_t>> range(T);
+    for (int64_t t = 0; t < tiles; ++t) range[t % T].push_back((int32_t)t);
+    for (auto &v : range)
         std::stable_sort(v.begin(), v.end(), [&](int32_t a, int32_t c) {
             return hfirst[a + 1] - hfirst[a] > hfirst[c + 1] - hfirst[c];
         });
     std::vector<int32_t> order;
-    size_t take[T] = {0, 0};
+    std::vector<size_t> take(T, 0);
     for (int64_t w = 0; w < tiles; ++w) {
-        int hh = (w % 8) < 4 ? 0 : 1;
-        if (take[hh] == half[hh].size()) hh = 1 - hh;
-        order.push_back(half[hh][take[hh]++]);
+        int hh = (int)((w % 8) * T / 8);
+        for (int k = 0; k < T && take[hh] == range[hh].size(); ++k) hh = (hh + 1) % T;
+        order.push_back(range[hh][take[hh]++]);
     }
     P.blk_order.alloc(std::max<int64_t>(tiles, 1) * 4);
     if (tiles > 0)
@@ -852,7 +873,7 @@ void build_sorted_tiles(spmv_matrix_s *h, hipStream_t s) {
     P.idx.alloc(cap * 4);
     P.val.alloc(cap * vs);
     P.chunk_base.alloc(std::max<int64_t>(total / kSortedChunk, 1) * 4);
-    P.partial.alloc(std::max<int64_t>(n, 1) * vs);
+    P.partial.alloc((T - 1) * P.pitch * vs);
     SPMV_HIP(hipMemsetAsync(P.idx.p, 0xFF, cap * 4, s));  // kPanelPad
     SPMV_HIP(hipMemsetAsync(P.val.p, 0, cap * vs, s));
     SPMV_HIP(hipMemsetAsync(P.chunk_base.p, 0, std::max<int64_t>(total / kSortedChunk, 1) * 4, s));
@@ -865,27 +886,27 @@ void build_sorted_tiles(spmv_matrix_s *h, hipStream_t s) {
             tiles_scatter<double><<<grid_of_n(nnz), kB, 0, s>>>(
                 keys.as<uint64_t>(), perm.as<uint32_t>(), nnz, key_bits, h->row.as<int32_t>(),
                 h->val.as<double>(), first.as<int32_t>(), start.as<int32_t>(),
-                P.blk_row.as<int32_t>(), P.delta, P.col_bits, P.idx.as<int32_t>(),
+                P.blk_row.as<int32_t>(), T == 4 ? 2 : 1, P.delta, P.col_bits, P.idx.as<int32_t>(),
                 P.rows16.as<uint16_t>(), P.chunk_base.as<int32_t>(), P.val.as<double>());
         else
             tiles_scatter<float><<<grid_of_n(nnz), kB, 0, s>>>(
                 keys.as<uint64_t>(), perm.as<uint32_t>(), nnz, key_bits, h->row.as<int32_t>(),
                 h->val.as<float>(), first.as<int32_t>(), start.as<int32_t>(),
-                P.blk_row.as<int32_t>(), P.delta, P.col_bits, P.idx.as<int32_t>(),
+                P.blk_row.as<int32_t>(), T == 4 ? 2 : 1, P.delta, P.col_bits, P.idx.as<int32_t>(),
                 P.rows16.as<uint16_t>(), P.chunk_base.as<int32_t>(), P.val.as<float>());
         SPMV_CHECK_LAUNCH();
     }
     P.blk_ptr = std::move(start);
     SPMV_HIP(hipStreamSynchronize(s));  // also keeps `order` alive until its copy is done
     P.built = true;
-    h->sorted_tiles = std::move(P);
+    h->sorted_tiles[T == 4] = std::move(P);
 }
 
-void sorted_tiles_spmv(const spmv_matrix_s *h, int items, double alpha, const void *x, double beta,
-                       void *y, hipStream_t s) {
-    if (!h->sorted_tiles.built) fail(SPMV_ERR_NOT_CONVERTED, "column-tile layout not built");
+void sorted_tiles_spmv(const spmv_matrix_s *h, int tiles, int items, double alpha, const void *x,
+                       double beta, void *y, hipStream_t s) {
+    const SortedPart &P = h->sorted_tiles[tiles == 4];
+    if (!P.built) fail(SPMV_ERR_NOT_CONVERTED, "column-tile layout not built");
     if (h->n_rows == 0) return;
-    const SortedPart &P = h->sorted_tiles;
     if (h->dt == SPMV_F64) {
         if (items == 8) launch_tiles<double, 8>(P, h->n_rows, alpha, x, beta, y, s);
         else launch_tiles<double, 16>(P, h->n_rows, alpha, x, beta, y, s);

@@ -118,7 +118,9 @@ double tune_format(spmv_matrix_s *h, spmv_format f, const void *x, void *y, int3
         SPMV_HIP(hipStreamSynchronize(s));
         if (h->panel.built && !variant_needs_panel(f, bi)) h->panel = PanelPart{};
         if (h->sorted.built && !variant_needs_sorted(f, bi)) h->sorted = SortedPart{};
-        if (h->sorted_tiles.built && !variant_needs_sorted_tiles(f, bi)) h->sorted_tiles = SortedPart{};
+        for (int k = 0; k < 2; ++k)
+            if (h->sorted_tiles[k].built && variant_sorted_tiles(f, bi) != (k ? 4 : 2))
+                h->sorted_tiles[k] = SortedPart{};
         if (h->split.built && !variant_needs_split(f, bi)) h->split = SplitPart{};
     }
     if (f == SPMV_FMT_HYB && h->hyb_sorted.built && !variant_needs_hyb_sorted(f, bi)) {
