@@ -1253,6 +1253,7 @@ template <class V> void sell_k16(const Args &a) { sell_ksplit_launch<V, 16, 1, t
 BELLV(1, 256, 1) BELLV(2, 256, 1) BELLV(4, 256, 1) BELLV(1, 256, 2) BELLV(2, 256, 2) BELLV(4, 256, 2)
 BELLV(1, 64, 1) BELLV(1, 128, 1) BELLV(1, 512, 1) BELLV(1, 1024, 1)
 BELLV(2, 64, 1) BELLV(2, 128, 1) BELLV(2, 512, 1) BELLV(2, 1024, 1)
+BELLV(1, 256, 4) BELLV(1, 128, 2) BELLV(1, 64, 2) BELLV(2, 256, 4)
 #undef BELLV
 
 #define VS(blk, unr, pipe, ks, fn) \
@@ -1381,6 +1382,8 @@ const std::vector<Variant> &table(spmv_format f) {
         VB(1024, 1, 1, bell_1_1024_1),
         VB(64, 2, 1, bell_2_64_1), VB(128, 2, 1, bell_2_128_1), VB(512, 2, 1, bell_2_512_1),
         VB(1024, 2, 1, bell_2_1024_1),
+        VB(256, 1, 4, bell_1_256_4), VB(128, 1, 2, bell_1_128_2), VB(64, 1, 2, bell_1_64_2),
+        VB(256, 2, 4, bell_2_256_4),
     };
     static const std::vector<Variant> none;
     switch (f) {
