@@ -156,3 +156,29 @@ def test_trace_summary_adds_the_kernels_of_one_launch(tmp_path, capsys):
     out = capsys.readouterr().out
     assert "rocprofv3 average duration over the timed launches: 23.000 us" in out
     assert "achieved from rocprofv3 duration: 4347.8 GB/s" in out
+
+
+def test_counter_summary_adds_the_kernels_of_one_launch(tmp_path, capsys):
+    """Two kernels per launch (column tiles and their combine): each kernel's last `launches`
+    dispatches are averaged and the two means added."""
+    k1 = "void spmv::coo_tiles_kernel<float, 8, false, true>(int)"
+    k2 = "void spmv::sorted_tiles_combine<float>(long)"
+    copy = "__amd_rocclr_copyBuffer"
+    _counter_csv(tmp_path / "f.csv", "FETCH_SIZE",
+                 [(k1, 1.0), (k2, 1.0), (k1, 1000.0), (k2, 100.0), (k1, 3000.0), (k2, 300.0)]
+                 + [(copy, 2048.0)] * 3)
+    _counter_csv(tmp_path / "w.csv", "WRITE_SIZE",
+                 [(k1, 1.0), (k2, 1.0), (k1, 10.0), (k2, 50.0), (k1, 30.0), (k2, 150.0)]
+                 + [(copy, 4096.0)] * 3)
+    (tmp_path / "b.json").write_text(json.dumps({
+        "copy_calibration_mib": 4,
+        "roofline": {"kernel": "coo_tiles_kernel_f32", "kernel_symbol": "coo_tiles_kernel<float, ",
+                     "kernel_symbols": ["coo_tiles_kernel<float, ", "sorted_tiles_combine<float>"],
+                     "launches": 2, "bytes_per_launch": 4.0e6}}) + "\n")
+    bench.counter_summary(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"),
+                          str(tmp_path / "b.json"), str(tmp_path / "t.json"))
+    t = json.loads((tmp_path / "t.json").read_text())
+    # fetch (2000 + 200) x 2, write 20 + 100, per launch
+    assert t["kernels"]["coo_tiles_kernel_f32"] == ((2000.0 + 200.0) * 2.0 + 20.0 + 100.0) * 1024
+    assert bench.kernel_source_hash("coo_tiles_kernel_f32") == bench.kernel_source_hash("coo_sorted_kernel_f32")
+    assert "coo_tiles_kernel<float,  + sorted_tiles_combine<float>" in capsys.readouterr().out
