@@ -33,7 +33,7 @@ HBM_PEAK_GBPS = 8000.0
 METRIC = "SpMV effective HBM GB/s (% of peak) per format; selector regret vs exhaustive"
 FMT_NAMES = ("CSR", "COO", "ELL", "HYB", "SELL", "BELL")
 NF = len(FMT_NAMES)
-NF4 = 4  # the selector network's classes of the spec formats: CSR, COO, ELL, HYB
+NF4 = 4  # the 4-class selector network's formats: CSR, COO, ELL, HYB
 
 
 def format_bytes(fmt, n_rows, n_cols, nnz, vb, K=0, pitch=0, tail=0):

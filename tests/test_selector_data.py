@@ -105,7 +105,7 @@ def test_six_format_dataset_and_network():
     """The six-format collection (CSR, COO, ELL, HYB, SELL, BELL on the selector seeds) and
     the 6-class network trained from it: the network's predictions, recomputed by the FP64
     oracle, stay within 5% of the best on the held-out matrices and beat always-CSR, the
-    rule and the best of the four spec formats alone."""
+    rule and the best of CSR, COO, ELL and HYB alone."""
     d = dict(np.load(DATA6, allow_pickle=False))
     assert d["feats"].shape == (2000, 12) and d["t_label"].shape == (2000, 6)
     assert np.all(np.isfinite(d["t_label"][:, [0, 1, 3]]))
