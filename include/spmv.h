@@ -264,8 +264,10 @@ spmv_status spmv_tune(spmv_handle h, spmv_format f, const void *x, void *y, int3
 /* Bytes of the device arrays one run of format f with `variant` (-1 = the
  * current one) reads besides x and y: the layout that variant streams (the
  * format arrays, or the reordered copy it uses, with their padding) and its
- * pointer and order arrays. A run's algorithmic bytes are this plus n_cols
- * values of x and n_rows of y (twice when beta != 0).
+ * pointer and order arrays; for column tiles also the other ranges' row sums
+ * written and read back and y's second pass (2 (tiles - 1) + 2 values per
+ * row). A run's algorithmic bytes are this plus n_cols values of x and n_rows
+ * of y (twice when beta != 0).
  *   bytes: host pointer. Errors: INVALID_ARG, NOT_CONVERTED (the format, or
  *   the copy the variant reads, is not built). Touches no device memory. */
 spmv_status spmv_stored_bytes(spmv_handle h, spmv_format f, int32_t variant, int64_t *bytes);
