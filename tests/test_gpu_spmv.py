@@ -284,6 +284,40 @@ def test_column_tiles_with_unaligned_y(dtype):
         assert OS.max_row_error(g[1:-1], y_ref, den) <= C.TOL[dtype], var
 
 
+def test_four_column_tiles_refused_past_the_lds_rows():
+    """Four column tiles need blocks of 4 n / 256 rows, at most 16384 (the FP64 row sums of a
+    block fill 128 KB of LDS): a 1.1M-row matrix is refused four tiles (NOT_APPLICABLE) and
+    runs in two, within the bound of the oracle."""
+    n_rows, n_cols = 1_100_000, 4000
+    rng = np.random.default_rng(44)
+    row = np.arange(n_rows, dtype=np.int64)
+    col = rng.integers(0, n_cols, n_rows)
+    m = synth.from_coords("tall_single", n_rows, n_cols, row, col, 45)
+    v = m.values(np.float32)
+    print(f"[spmv tiles limit] {n_rows} x {n_cols}", flush=True)
+    h = S.spmv_create(m.n_rows, m.n_cols, m.row, m.col, v)
+    x = synth.uniform_vector(n_cols, np.float32, [44, 3])
+    xd = torch.from_numpy(x).cuda()
+    c = OF.canonicalize(n_rows, n_cols, m.row, m.col, v)
+    y_ref = OS.spmv_csr(c["row_ptr"], c["col"], c["val"], x, np.float32(1.0), np.float32(0.0), None)
+    den = OS.row_denominator(c["row_ptr"], c["col"], c["val"], x, np.float32(1.0), np.float32(0.0), None)
+    by_tiles = {}
+    for i in range(S.spmv_variant_count(S.SPMV_FMT_COO, h.dtype_code)):
+        d = S.spmv_variant_describe(S.SPMV_FMT_COO, h.dtype_code, i)
+        if d["kernel"] == "coo_sorted" and d["ksplit"] > 1:
+            by_tiles.setdefault(d["ksplit"], []).append(i)
+    assert sorted(by_tiles) == [2, 4]
+    for var in by_tiles[4]:
+        with pytest.raises(S.SpmvError) as e:
+            S.spmv_set_variant(h, S.SPMV_FMT_COO, var)
+        assert e.value.status == "NOT_APPLICABLE"
+    for var in by_tiles[2]:
+        S.spmv_set_variant(h, S.SPMV_FMT_COO, var)
+        yd = torch.zeros(n_rows, dtype=torch.float32, device="cuda")
+        S.spmv_run(h, S.SPMV_FMT_COO, 1.0, xd, 0.0, yd)
+        assert OS.max_row_error(yd.cpu().numpy(), y_ref, den) <= C.TOL[np.float32], var
+
+
 def test_reordered_coo_layouts_at_their_column_limits():
     """Streaming COO packs columns in 23 bits and refuses wider matrices; sorted-block COO
     packs the row in the bits the column leaves free and still runs."""
