@@ -216,6 +216,10 @@ spmv_status spmv_convert(spmv_handle h, spmv_format f, int32_t param, void *stre
  *      ignores NaN or garbage in y. x and y must not overlap.
  *   alpha, beta: rounded to the handle's dtype.
  * Rows with no entries get y = beta * y (or 0 when beta == 0).
+ * A run only launches kernels on `stream` (it never allocates, copies,
+ * fills or synchronises; the variant's layout is built beforehand by
+ * spmv_convert / spmv_set_variant / spmv_tune), so it may be captured into a
+ * HIP graph and replayed.
  * Errors: INVALID_ARG (NULL x/y with a nonzero dimension, x and y overlap),
  *         NOT_CONVERTED, HIP (launch failure). */
 spmv_status spmv_run(spmv_handle h, spmv_format f, double alpha, const void *x, double beta,
