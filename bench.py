@@ -916,7 +916,10 @@ def main():
     # at each change of instance, which gives each instance its own achieved rate.
     def instance(e):
         info = S.spmv_variant_describe(e["fmt"], S.SPMV_F32, e["variant"][e["fmt"]])
-        return kernel_symbols(e["fmt"], info)[0]
+        sym = kernel_symbols(e["fmt"], info)[0]
+        if sym.startswith("coo_tiles_kernel<"):  # the tile count is a launch argument
+            sym += f"... ({info['ksplit']} tiles)"
+        return sym
 
     order = sorted(range(len(mats)),
                    key=lambda i: (i not in members, instance(mats[i]) if i in members else "", i))
